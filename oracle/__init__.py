@@ -1,0 +1,220 @@
+"""CPU oracle for exact Kendall's tau -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares nothing with the HIP library
+in ``paper_1704_03767_amd``: its arithmetic lives in ``ktau_oracle.c`` (plain
+C, compiled here with gcc), and this module only marshals numpy arrays.
+
+Two pair routines, both from the paper:
+  * ``"brute"`` -- the definition of concordant / discordant / tied pairs
+    (Sec. 1, and the naive kernel of Sec. 3.1 generalised to all five counts);
+  * ``"gse"``   -- the sorting-enabled kernel, Steps 1-5 of Sec. 3.2 with the
+    merge of Algorithm 2.
+tau_B (Eq. 3) and tau_A (Eq. 1) follow from the integer counts.
+
+Pins (tests/test_oracle.py): brute == gse on exhaustive tiny domains; closed
+forms (inversion count of a permutation built from its Lehmer code, reversal,
+adjacent swap); invariants (self = 1, negation = -1, symmetry, sample
+permutation, exact monotone maps, partition identity); scipy.stats.kendalltau
+and numpy.unique tie-group counts as independent library routines.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ktau_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libktau_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+KO_OK = 0
+KO_EINVAL = -1
+KO_ENOMEM = -3
+KO_ENAN = -6
+
+METHODS = {"brute": 0, "gse": 1}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = True) -> str:
+    """Compile ktau_oracle.c with gcc (plain -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+    ):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = [
+            "gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-ffp-contract=off",
+            "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm",
+        ]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        p = ctypes.c_void_p
+        lib.ko_pair_brute.argtypes = [p, p, i64, p]
+        lib.ko_pair_brute.restype = None
+        lib.ko_pair_gse.argtypes = [p, p, i64, p]
+        lib.ko_pair_gse.restype = i32
+        lib.ko_tau.argtypes = [p, i64, p, p]
+        lib.ko_tau.restype = None
+        lib.ko_allpairs.argtypes = [p, i64, i64, i32, i32, p, p, p, p, p, p]
+        lib.ko_allpairs.restype = i32
+        lib.ko_pairs.argtypes = [p, i64, i64, p, p, i64, i32, i32, p, p, p, p, p, p, p]
+        lib.ko_pairs.restype = i32
+        lib.ko_rank_rows.argtypes = [p, i64, i64, p, p, p]
+        lib.ko_rank_rows.restype = i32
+        lib.ko_query_topk.argtypes = [p, i64, i64, p, i64, i64, i32, p, p, p]
+        lib.ko_query_topk.restype = i32
+        lib.ko_enumerate_pairs.argtypes = [i64, p, p]
+        lib.ko_enumerate_pairs.restype = i32
+        lib.ko_max_threads.argtypes = []
+        lib.ko_max_threads.restype = i32
+        _lib = lib
+        return lib
+
+
+class _Counts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("nc", "nd", "n1", "n2", "n3")]
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _check(rc: int, what: str):
+    if rc != KO_OK:
+        raise OracleError(f"{what} failed with status {rc}")
+
+
+def max_threads() -> int:
+    return int(_load().ko_max_threads())
+
+
+def pair_counts(u, v, method: str = "gse") -> dict:
+    """Counts nc, nd, n1, n2, n3 for one pair of equal-length vectors."""
+    lib = _load()
+    u = _f32(u)
+    v = _f32(v)
+    if u.shape != v.shape or u.ndim != 1:
+        raise ValueError("u and v must be 1-D of equal length")
+    if np.isnan(u).any() or np.isnan(v).any():
+        raise OracleError("NaN input")
+    c = _Counts()
+    if method == "brute":
+        lib.ko_pair_brute(_ptr(u), _ptr(v), u.size, ctypes.byref(c))
+    elif method == "gse":
+        _check(lib.ko_pair_gse(_ptr(u), _ptr(v), u.size, ctypes.byref(c)), "ko_pair_gse")
+    else:
+        raise ValueError(method)
+    return {k: int(getattr(c, k)) for k in ("nc", "nd", "n1", "n2", "n3")}
+
+
+def tau(counts: dict, n: int) -> tuple[float, float]:
+    """(tau_B, tau_A) from integer counts (Eq. 3, Eq. 1)."""
+    lib = _load()
+    c = _Counts(*(counts[k] for k in ("nc", "nd", "n1", "n2", "n3")))
+    tb = ctypes.c_double()
+    ta = ctypes.c_double()
+    lib.ko_tau(ctypes.byref(c), int(n), ctypes.byref(tb), ctypes.byref(ta))
+    return float(tb.value), float(ta.value)
+
+
+def allpairs(X, method: str = "gse", threads: int = 0) -> dict:
+    """All strict pairs y < x of the rows of X, in row-major job order."""
+    lib = _load()
+    X = _f32(X)
+    m, n = X.shape
+    P = m * (m - 1) // 2
+    out = {
+        "nc": np.empty(P, np.int64), "nd": np.empty(P, np.int64),
+        "n3": np.empty(P, np.int64), "tau_b": np.empty(P, np.float64),
+        "tau_a": np.empty(P, np.float64), "n1": np.empty(m, np.int64),
+    }
+    rc = lib.ko_allpairs(
+        _ptr(X), m, n, METHODS[method], int(threads), _ptr(out["nc"]), _ptr(out["nd"]),
+        _ptr(out["n3"]), _ptr(out["tau_b"]), _ptr(out["tau_a"]), _ptr(out["n1"]),
+    )
+    _check(rc, "ko_allpairs")
+    return out
+
+
+def pairs(X, ys, xs, method: str = "gse", threads: int = 0) -> dict:
+    """Selected pairs (ys[i], xs[i]) with u = row ys[i], v = row xs[i]."""
+    lib = _load()
+    X = _f32(X)
+    m, n = X.shape
+    ys = np.ascontiguousarray(ys, dtype=np.int64)
+    xs = np.ascontiguousarray(xs, dtype=np.int64)
+    cnt = ys.size
+    out = {k: np.empty(cnt, np.int64) for k in ("nc", "nd", "n3", "n1", "n2")}
+    out["tau_b"] = np.empty(cnt, np.float64)
+    out["tau_a"] = np.empty(cnt, np.float64)
+    rc = lib.ko_pairs(
+        _ptr(X), m, n, _ptr(ys), _ptr(xs), cnt, METHODS[method], int(threads),
+        _ptr(out["nc"]), _ptr(out["nd"]), _ptr(out["n3"]), _ptr(out["n1"]),
+        _ptr(out["n2"]), _ptr(out["tau_b"]), _ptr(out["tau_a"]),
+    )
+    _check(rc, "ko_pairs")
+    return out
+
+
+def rank_rows(X) -> dict:
+    """Per row: stable ascending order, dense ranks, and the tie term n1."""
+    lib = _load()
+    X = _f32(X)
+    m, n = X.shape
+    order = np.empty((m, n), np.int32)
+    rank = np.empty((m, n), np.int32)
+    n1 = np.empty(m, np.int64)
+    _check(lib.ko_rank_rows(_ptr(X), m, n, _ptr(order), _ptr(rank), _ptr(n1)), "ko_rank_rows")
+    return {"order": order, "rank": rank, "n1": n1}
+
+
+def query_topk(db, Q, k: int, threads: int = 0) -> dict:
+    """Top-k database rows by |tau_B| for every query row."""
+    lib = _load()
+    db = _f32(db)
+    Q = _f32(Q)
+    if Q.ndim == 1:
+        Q = Q[None, :]
+    m, n = db.shape
+    nq = Q.shape[0]
+    idx = np.empty((nq, k), np.int64)
+    tb = np.empty((nq, k), np.float64)
+    nd = np.empty((nq, k), np.int64)
+    rc = lib.ko_query_topk(_ptr(db), m, n, _ptr(Q), nq, int(k), int(threads),
+                           _ptr(idx), _ptr(tb), _ptr(nd))
+    _check(rc, "ko_query_topk")
+    return {"idx": idx, "tau": tb, "nd": nd}
+
+
+def enumerate_pairs(m: int) -> tuple[np.ndarray, np.ndarray]:
+    """(y, x) of every strict job, in row-major order."""
+    lib = _load()
+    P = m * (m - 1) // 2
+    ys = np.empty(P, np.int64)
+    xs = np.empty(P, np.int64)
+    _check(lib.ko_enumerate_pairs(int(m), _ptr(ys), _ptr(xs)), "ko_enumerate_pairs")
+    return ys, xs
