@@ -1,0 +1,158 @@
+/*
+ * ktau.h -- exact all-pairs Kendall's tau on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: Liu, Pan, Green, Aluru, "Parallelized Kendall's Tau Coefficient
+ * Computation via SIMD Vectorized Sorting on Many-Integrated-Core Processors".
+ *
+ * Given m variables observed on n samples (a row-major m x n float32 matrix,
+ * one row per variable), the library computes for every strict pair of rows
+ * y < x the exact integer counts of Sec. 1 and Table 1 -- concordant n_c,
+ * discordant n_d, joint ties n3 -- and the per-row tie term n1 (n2 of a pair is
+ * n1 of its second row), and from them tau_B (Eq. 3) and optionally tau_A
+ * (Eq. 1) in FP64:
+ *     tau_B = (double)(nc - nd) / sqrt((double)(n0 - n1) * (double)(n0 - n2))
+ * with n0 = n(n-1)/2, round-to-nearest, no contraction; a constant row gives
+ * tau_B = NaN (0/0) while its counts stay exact.  Ties are IEEE float32
+ * equality (-0.0 ties +0.0).  NaN inputs are refused (KTAU_ENAN).
+ *
+ * Counts come from the sorting method of Sec. 3.2: samples ordered by u (a
+ * per-row rank pre-pass done once per row, Sec. 3), v permuted into that order,
+ * discordant pairs counted as strict inversions by merge sort (Algorithm 2),
+ * tie runs scanned.  Pairs are numbered by the job-id bijection of Sec. 4.1
+ * (Eq. 4-10) restricted to the strict upper triangle: row-major, y < x,
+ *     J(y, x) = F(y) + (x - y - 1),  F(y) = y (2(m-1) - y + 1) / 2,
+ * J in [0, m(m-1)/2).  Work is spread in q x q tiles numbered by Eq. 11-14.
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device (HBM) pointers owned by the caller unless
+ *     stated; host pointers are named *_host.  The library never frees caller
+ *     memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls that take a stream are asynchronous and stream-ordered: they
+ *     return after validating arguments and enqueueing kernels.
+ *   - Every call returns an int status: KTAU_OK (0) or a negative KTAU_E*.
+ *     Host-detectable errors are returned before anything is enqueued; NaN in
+ *     the input is found on the device, latched in the workspace header and
+ *     reported by ktau_status().  No C++ exception crosses this interface.
+ *   - Sizes: 2 <= n <= KTAU_MAX_N, m >= 2 (m < 2^31).
+ */
+#ifndef KTAU_H
+#define KTAU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KTAU_OK 0
+#define KTAU_EINVAL -1    /* bad argument: null pointer, m < 2, n < 2, bad range */
+#define KTAU_ERANGE -2    /* n > KTAU_MAX_N, or a job range outside [0, P]      */
+#define KTAU_ENOMEM -3    /* workspace too small or a device allocation failed  */
+#define KTAU_EDEVICE -4   /* a HIP runtime call failed                          */
+#define KTAU_EBUSY -5     /* server: non-blocking submit refused by admission   */
+#define KTAU_ENAN -6      /* a NaN was found in the input (latched on device)   */
+#define KTAU_ECANCELED -7 /* server: request cancelled or failed in its slot    */
+#define KTAU_ETIMEDOUT -8 /* server: wait timed out                             */
+
+/* Largest sample count n supported by the rank pre-pass and pair kernels. */
+#define KTAU_MAX_N 4096
+
+/* Human-readable name of a status code (static storage). */
+const char* ktau_status_string(int status);
+
+/* ---------------------------------------------------------------------------
+ * Job-id bijection (Sec. 4.1, Eq. 4-10; tiles Sec. 4.2, Eq. 11-14).  Host
+ * functions; the kernels use the same arithmetic on the device.
+ * ------------------------------------------------------------------------- */
+
+/* Strict job id of pair (y, x), 0 <= y < x < m; -1 if the pair is invalid. */
+int64_t ktau_pair_to_job(int64_t m, int64_t y, int64_t x);
+
+/* Inverse of ktau_pair_to_job: Eq. 9 on dimension m-1 evaluated in FP64,
+ * then an exact integer fix-up.  KTAU_ERANGE if J is not in [0, m(m-1)/2). */
+int ktau_job_to_pair(int64_t m, int64_t J, int64_t* y_host, int64_t* x_host);
+
+/* Inclusive tile triangle of a w x w tile matrix (Eq. 11-14): tile id t in
+ * [0, w(w+1)/2) -> tile coordinate yq <= xq.  KTAU_ERANGE if t is outside. */
+int ktau_tile_to_coord(int64_t w, int64_t t, int64_t* yq_host, int64_t* xq_host);
+
+/* ---------------------------------------------------------------------------
+ * Rank pre-pass (Sec. 3: every vector is replaced by its ranks once).
+ * ------------------------------------------------------------------------- */
+
+/* For each row r of X_dev (m x n float32, row-major, contiguous):
+ *   perm_dev[r*n + k]   = sample at sorted position k (ascending value, equal
+ *                         values by sample index), uint16;
+ *   rank_dev[r*n + i]   = dense rank of sample i (number of distinct values
+ *                         below it), uint16;
+ *   rstart_dev[r*n + k] = first sorted position of the tie run holding
+ *                         position k, uint16;
+ *   n1_dev[r]           = sum over tie runs of t(t-1)/2, int64.
+ * Any output may be NULL.  status_dev (int32, device) receives KTAU_ENAN if a
+ * NaN is present (written only on error; the caller clears it). */
+int ktau_rank(const float* X_dev, int64_t m, int64_t n, uint16_t* perm_dev,
+              uint16_t* rank_dev, uint16_t* rstart_dev, int64_t* n1_dev,
+              int32_t* status_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Plain all-pairs.
+ * ------------------------------------------------------------------------- */
+
+/* Result arrays, all device pointers; any may be NULL to skip it.  Pair
+ * arrays hold one entry per strict job id (J - J_begin for range calls). */
+typedef struct ktau_pair_out {
+  int64_t* nc;     /* concordant pairs                       [P]  */
+  int64_t* nd;     /* discordant pairs                       [P]  */
+  int64_t* n3;     /* pairs tied in both rows                [P]  */
+  double* tau_b;   /* tau_B (Eq. 3)                          [P]  */
+  double* tau_a;   /* tau_A (Eq. 1)                          [P]  */
+  int64_t* n1;     /* per-row tie term; n2 of (y, x) = n1[x] [m]  */
+} ktau_pair_out;
+
+/* Bytes of device workspace the all-pairs calls need for (m, n). */
+size_t ktau_allpairs_workspace_size(int64_t m, int64_t n);
+
+/* All m(m-1)/2 strict pairs of X_dev (m x n float32, row-major).  The
+ * workspace (>= ktau_allpairs_workspace_size bytes, 256-byte aligned, owned by
+ * the caller) receives the rank pre-pass and the status word; it may be
+ * reused across calls once the previous call on it has completed. */
+int ktau_allpairs(const float* X_dev, int64_t m, int64_t n, ktau_pair_out out,
+                  void* workspace_dev, size_t ws_bytes, void* stream);
+
+/* Jobs J in [J_begin, J_end) only (Sec. 4.3 multi-pass sub-ranges); result
+ * slot of job J is J - J_begin.  Any prefix of the job range can be resumed
+ * from its end. */
+int ktau_allpairs_range(const float* X_dev, int64_t m, int64_t n,
+                        int64_t J_begin, int64_t J_end, ktau_pair_out out,
+                        void* workspace_dev, size_t ws_bytes, void* stream);
+
+/* Waits for `stream`, then returns the status latched in a workspace by the
+ * last call that used it (KTAU_ENAN if the input held a NaN, else KTAU_OK),
+ * and clears it. */
+int ktau_status(void* workspace_dev, void* stream);
+
+
+/* ---------------------------------------------------------------------------
+ * Per-pair schemes and an explicit-scheme entry point (for tuning and tests).
+ * A scheme is a group size (one 64-lane wave, or a 256-lane workgroup) and a
+ * number K of keys per lane; it handles n <= lanes * K.
+ * ------------------------------------------------------------------------- */
+
+int ktau_scheme_count(void);
+const char* ktau_scheme_name(int scheme);      /* "invalid" if out of range   */
+int64_t ktau_scheme_capacity(int scheme);      /* largest n; -1 if invalid    */
+int ktau_default_scheme(int64_t n);
+
+/* ktau_allpairs (J_begin < 0) or ktau_allpairs_range (J_begin >= 0) with the
+ * scheme and tile edge q (1..64) chosen by the caller; scheme < 0 or q <= 0
+ * pick the defaults.  KTAU_EINVAL if the scheme cannot hold n. */
+int ktau_allpairs_ex(const float* X_dev, int64_t m, int64_t n, int64_t J_begin,
+                     int64_t J_end, ktau_pair_out out, void* workspace_dev,
+                     size_t ws_bytes, int scheme, int q, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KTAU_H */

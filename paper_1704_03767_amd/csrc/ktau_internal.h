@@ -1,0 +1,140 @@
+// Internal declarations shared by the HIP translation units of libktau.
+// Nothing here is part of the public interface (include/ktau.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ktau.h"
+
+namespace ktau {
+
+// Rows of every per-variable array are padded to a multiple of this many
+// uint16 elements, so each row starts on a 128-byte boundary.
+constexpr int64_t kRowAlign = 64;
+constexpr size_t kWsHeader = 256;       // bytes: status word + reserved
+constexpr size_t kAlign = 256;
+
+// Sort keys: padding slots beyond n, and the sentinel read past a run end.
+// Real keys are at most 0x0FFFFFFF (16-bit tie-run id << 16 | 16-bit rank,
+// with n <= KTAU_MAX_N), so both compare above every real key and the
+// sentinel above the padding.
+constexpr uint32_t kPadKey = 0xFFFFFFFEu;
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+
+__host__ __device__ inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// ---- job-id bijection (Sec. 4.1, Eq. 4-10) and tiles (Sec. 4.2, Eq. 11-14)
+
+// Cells before row y of the inclusive upper triangle of a d x d matrix (Eq. 5).
+__host__ __device__ inline int64_t tri_row_start(int64_t d, int64_t y) {
+  return y * (2 * d - y + 1) / 2;
+}
+
+// Row of inclusive-triangle id t in a d x d matrix: Eq. 9 in FP64, then an
+// exact integer correction so rounding in sqrt can never pick the wrong row.
+__host__ __device__ inline int64_t tri_row_of(int64_t d, int64_t t) {
+  double dd = (double)d;
+  double z = dd - 0.5 - sqrt(dd * dd + dd + 0.25 - 2.0 * (double)(t + 1));
+  int64_t y = (int64_t)ceil(z);
+  if (y < 0) y = 0;
+  if (y > d - 1) y = d - 1;
+  while (y > 0 && tri_row_start(d, y) > t) --y;
+  while (y + 1 < d && tri_row_start(d, y + 1) <= t) ++y;
+  return y;
+}
+
+// Strict triangle of an m x m matrix = inclusive triangle of dimension m-1
+// with x shifted by one: J = F_{m-1}(y) + (x - 1 - y).
+__host__ __device__ inline int64_t strict_job(int64_t m, int64_t y, int64_t x) {
+  return tri_row_start(m - 1, y) + (x - 1 - y);
+}
+
+__host__ __device__ inline void strict_pair(int64_t m, int64_t J, int64_t& y, int64_t& x) {
+  y = tri_row_of(m - 1, J);
+  x = J - tri_row_start(m - 1, y) + y + 1;
+}
+
+__host__ __device__ inline void tile_coord(int64_t w, int64_t t, int64_t& yq, int64_t& xq) {
+  yq = tri_row_of(w, t);
+  xq = t - tri_row_start(w, yq) + yq;
+}
+
+// ---- device views
+
+struct RankView {
+  const uint16_t* perm;     // [rows][ld] sorted position -> sample
+  const uint16_t* rank;     // [rows][ld] sample -> dense rank
+  const uint16_t* rstart;   // [rows][ld] sorted position -> first position of its tie run
+  const int64_t* n1;        // [rows]
+  int64_t ld;               // row stride in elements
+};
+
+struct PairOut {
+  int64_t* nc;
+  int64_t* nd;
+  int64_t* n3;
+  double* tau_b;
+  double* tau_a;
+};
+
+// Per-pair schemes.  A "group" of G lanes (one wave, or a whole 256-lane
+// block) sorts one pair's n <= G*K keys, K keys per lane.
+enum Scheme : int32_t {
+  kWaveK2 = 0,
+  kWaveK4 = 1,
+  kWaveK8 = 2,
+  kWaveK16 = 3,
+  kBlockK4 = 4,
+  kBlockK8 = 5,
+  kBlockK16 = 6,
+  kNumSchemes = 7
+};
+
+inline int scheme_lanes(int s) { return s <= kWaveK16 ? 64 : 256; }
+inline int scheme_k(int s) {
+  static const int k[] = {2, 4, 8, 16, 4, 8, 16};
+  return k[s];
+}
+inline int64_t scheme_capacity(int s) { return (int64_t)scheme_lanes(s) * scheme_k(s); }
+const char* scheme_name(int s);
+int default_scheme(int64_t n);
+
+// Matrix descriptor for the persistent batched kernel.
+struct BatchDesc {
+  RankView rv;
+  PairOut out;
+  int64_t m;
+  int32_t n;
+  int32_t scheme;
+  int32_t q;            // tile edge
+  int32_t pad;
+  int64_t w;            // tiles per side
+  int64_t unit_begin;   // first global unit id of this matrix
+  int64_t n_units;      // w (w + 1) / 2 tiles
+};
+
+// ---- launchers (stream-ordered; return hipError_t)
+
+hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
+                          uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
+                          int32_t* status, hipStream_t s);
+
+// Plain launch over tiles [tile_begin, tile_begin + tile_count) of matrix m.
+hipError_t launch_pairs_tiles(int scheme, const RankView& rv, int64_t m, int n, int q, int64_t w,
+                              int64_t tile_begin, int64_t tile_count, const PairOut& out,
+                              const int32_t* status, hipStream_t s);
+
+// Plain launch over strict job ids [J_begin, J_end); results at J - J_begin.
+hipError_t launch_pairs_jobs(int scheme, const RankView& rv, int64_t m, int n, int64_t J_begin,
+                             int64_t J_end, const PairOut& out, const int32_t* status,
+                             hipStream_t s);
+
+// Persistent launch over all units of a descriptor table.
+hipError_t launch_pairs_batch(const BatchDesc* descs_dev, int64_t count, int64_t total_units,
+                              const int64_t* unit_prefix_dev, int64_t* counter_dev, int grid,
+                              int max_lanes, const int32_t* status, hipStream_t s);
+
+int persistent_grid(int max_lanes);
+
+}  // namespace ktau

@@ -1,0 +1,186 @@
+// Rank pre-pass: every variable is ranked once (Sec. 3), and the per-vector
+// half of the sorting kernel's Steps 1, 2 and 4 (Sec. 3.2) is done here once
+// per row instead of once per pair: the ascending order of the row (ties by
+// sample index), its dense ranks, the start of every tie run, and the tie term
+// n1 = sum t(t-1)/2.
+//
+// One 256-thread workgroup per row.  The row's (value key, sample) pairs are
+// bitonic-sorted in LDS as 64-bit words (order-preserving 32-bit key << 16 |
+// sample), then block scans produce dense ranks and run starts.
+#include "ktau_internal.h"
+
+namespace ktau {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Order-preserving map float32 -> uint32 with -0.0 folded onto +0.0 (IEEE
+// equality decides ties).  NaN never reaches a comparison: it is flagged.
+__device__ inline uint32_t float_key(float f, bool& nan) {
+  uint32_t b = __float_as_uint(f);
+  nan = (b & 0x7fffffffu) > 0x7f800000u;
+  if (b == 0x80000000u) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Block-wide exclusive scan (sum) of one int per thread; also returns the total.
+__device__ inline int block_excl_sum(int v, int* sh, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  if (lane == 63) sh[wave] = incl;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    int s = sh[w];
+    if (w < wave) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return base + incl - v;
+}
+
+// Block-wide exclusive scan (max) of one non-negative int per thread.
+__device__ inline int block_excl_max(int v, int* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl = max(incl, t);
+  }
+  int excl_in_wave = __shfl_up(incl, 1, 64);
+  if (lane == 0) excl_in_wave = 0;
+  if (lane == 63) sh[wave] = incl;
+  __syncthreads();
+  int base = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w)
+    if (w < wave) base = max(base, sh[w]);
+  __syncthreads();
+  return max(base, excl_in_wave);
+}
+
+__global__ void __launch_bounds__(kThreads)
+prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
+               uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
+               uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
+               int64_t* __restrict__ n1_out, int32_t* __restrict__ status) {
+  extern __shared__ uint64_t s_keys[];
+  __shared__ int s_scan[kThreads / 64];
+  __shared__ unsigned long long s_n1;
+  const int64_t row = blockIdx.x;
+  if (row >= m) return;
+  const float* x = X + row * (int64_t)n;
+  const int tid = threadIdx.x;
+
+  bool any_nan = false;
+  for (int i = tid; i < npow2; i += kThreads) {
+    uint64_t w = ~0ull;
+    if (i < n) {
+      bool nan;
+      uint32_t k = float_key(x[i], nan);
+      any_nan |= nan;
+      w = ((uint64_t)k << 16) | (uint64_t)i;
+    }
+    s_keys[i] = w;
+  }
+  if (tid == 0) s_n1 = 0;
+  if (__syncthreads_or(any_nan)) {
+    if (tid == 0) atomicExch(status, KTAU_ENAN);
+    return;
+  }
+
+  // Bitonic sort of npow2 64-bit words, ascending.
+  for (int k = 2; k <= npow2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < npow2; i += kThreads) {
+        int p = i ^ j;
+        if (p > i) {
+          uint64_t a = s_keys[i], b = s_keys[p];
+          bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s_keys[i] = b;
+            s_keys[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // Each thread owns `chunk` consecutive sorted positions.
+  const int chunk = npow2 / kThreads > 0 ? npow2 / kThreads : 1;
+  const int k0 = tid * chunk;
+  // Pass 1: count value changes (for dense ranks) and the last run start.
+  int changes = 0, last_start = 0;
+  for (int c = 0; c < chunk; ++c) {
+    int k = k0 + c;
+    if (k < n && k > 0 && (s_keys[k] >> 16) != (s_keys[k - 1] >> 16)) {
+      ++changes;
+      last_start = k;
+    }
+  }
+  int total_changes;
+  int rank_base = block_excl_sum(changes, s_scan, total_changes);
+  int start_base = block_excl_max(last_start, s_scan);
+  // Pass 2: write perm, rank and rstart; accumulate n1.
+  uint16_t* prow = perm ? perm + row * ld : nullptr;
+  uint16_t* rrow = rank ? rank + row * ld : nullptr;
+  uint16_t* srow = rstart ? rstart + row * ld : nullptr;
+  int r = rank_base, st = start_base;
+  unsigned long long ties = 0;
+  for (int c = 0; c < chunk; ++c) {
+    int k = k0 + c;
+    if (k < n) {
+      uint64_t w = s_keys[k];
+      int sample = (int)(w & 0xFFFFu);
+      if (k > 0 && (w >> 16) != (s_keys[k - 1] >> 16)) {
+        ++r;
+        st = k;
+      }
+      if (prow) prow[k] = (uint16_t)sample;
+      if (rrow) rrow[sample] = (uint16_t)r;
+      if (srow) srow[k] = (uint16_t)st;
+      ties += (unsigned long long)(k - st);
+    } else if (k < ld) {
+      if (prow) prow[k] = 0;
+      if (srow) srow[k] = (uint16_t)k;
+    }
+  }
+  // Padding of rows longer than the sort width (ld > npow2 never happens for
+  // the workspace layout, but callers may pass a wider ld).
+  for (int k = npow2 + tid; k < ld; k += kThreads) {
+    if (prow) prow[k] = 0;
+    if (srow) srow[k] = (uint16_t)k;
+  }
+  if (rrow)
+    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = 0;
+  atomicAdd(&s_n1, ties);
+  __syncthreads();
+  if (tid == 0) {
+    if (n1_ws) n1_ws[row] = (int64_t)s_n1;
+    if (n1_out) n1_out[row] = (int64_t)s_n1;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
+                          uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
+                          int32_t* status, hipStream_t s) {
+  int npow2 = 64;
+  while (npow2 < n) npow2 <<= 1;
+  size_t lds = (size_t)npow2 * sizeof(uint64_t);
+  hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)m), dim3(kThreads), lds, s, X, m, (int)n,
+                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, status);
+  return hipGetLastError();
+}
+
+}  // namespace ktau

@@ -1,0 +1,269 @@
+"""Python binding of libktau (include/ktau.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  PyTorch
+supplies device memory and the current HIP stream; all arithmetic of the
+method runs in the HIP kernels of libktau.so.  If the library is not built,
+every call raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libktau.so")
+
+KTAU_OK = 0
+KTAU_EINVAL = -1
+KTAU_ERANGE = -2
+KTAU_ENOMEM = -3
+KTAU_EDEVICE = -4
+KTAU_EBUSY = -5
+KTAU_ENAN = -6
+KTAU_ECANCELED = -7
+KTAU_ETIMEDOUT = -8
+KTAU_MAX_N = 4096
+
+_lock = threading.Lock()
+_lib = None
+
+
+class KtauError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class _PairOut(ctypes.Structure):
+    _fields_ = [
+        ("nc", ctypes.c_void_p), ("nd", ctypes.c_void_p), ("n3", ctypes.c_void_p),
+        ("tau_b", ctypes.c_void_p), ("tau_a", ctypes.c_void_p), ("n1", ctypes.c_void_p),
+    ]
+
+
+def _declare(lib):
+    i64, i32, p, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+    decl = {
+        "ktau_status_string": ([i32], ctypes.c_char_p),
+        "ktau_pair_to_job": ([i64, i64, i64], i64),
+        "ktau_job_to_pair": ([i64, i64, p, p], i32),
+        "ktau_tile_to_coord": ([i64, i64, p, p], i32),
+        "ktau_rank": ([p, i64, i64, p, p, p, p, p, p], i32),
+        "ktau_allpairs_workspace_size": ([i64, i64], sz),
+        "ktau_allpairs": ([p, i64, i64, _PairOut, p, sz, p], i32),
+        "ktau_allpairs_range": ([p, i64, i64, i64, i64, _PairOut, p, sz, p], i32),
+        "ktau_allpairs_ex": ([p, i64, i64, i64, i64, _PairOut, p, sz, i32, i32, p], i32),
+        "ktau_status": ([p, p], i32),
+        "ktau_scheme_count": ([], i32),
+        "ktau_scheme_name": ([i32], ctypes.c_char_p),
+        "ktau_scheme_capacity": ([i32], i64),
+        "ktau_default_scheme": ([i64], i32),
+    }
+    for name, (args, res) in decl.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+def lib():
+    """The loaded libktau.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is missing: build it with `python -m paper_1704_03767_amd.build`")
+            _lib = _declare(ctypes.CDLL(LIB_PATH))
+        return _lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return lib().ktau_status_string(int(status)).decode()
+    except RuntimeError:
+        return "library not loaded"
+
+
+def _check(rc: int, what: str):
+    if rc != KTAU_OK:
+        raise KtauError(rc, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_matrix(X: torch.Tensor) -> torch.Tensor:
+    if not isinstance(X, torch.Tensor) or X.device.type != "cuda":
+        raise TypeError("X must be a CUDA (HIP) tensor")
+    if X.dtype != torch.float32 or X.dim() != 2:
+        raise TypeError("X must be a 2-D float32 tensor")
+    return X.contiguous()
+
+
+# ------------------------------------------------------------------ mapper
+
+
+def ktau_pair_to_job(m: int, y: int, x: int) -> int:
+    return int(lib().ktau_pair_to_job(m, y, x))
+
+
+def ktau_job_to_pair(m: int, J: int) -> tuple[int, int]:
+    y, x = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().ktau_job_to_pair(m, J, ctypes.byref(y), ctypes.byref(x)), "ktau_job_to_pair")
+    return y.value, x.value
+
+
+def ktau_tile_to_coord(w: int, t: int) -> tuple[int, int]:
+    y, x = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().ktau_tile_to_coord(w, t, ctypes.byref(y), ctypes.byref(x)), "ktau_tile_to_coord")
+    return y.value, x.value
+
+
+def ktau_scheme_names() -> list[str]:
+    L = lib()
+    return [L.ktau_scheme_name(i).decode() for i in range(L.ktau_scheme_count())]
+
+
+def ktau_scheme_capacity(scheme: int) -> int:
+    return int(lib().ktau_scheme_capacity(int(scheme)))
+
+
+def ktau_default_scheme(n: int) -> int:
+    return int(lib().ktau_default_scheme(int(n)))
+
+
+def scheme_id(scheme) -> int:
+    if scheme is None:
+        return -1
+    if isinstance(scheme, str):
+        return ktau_scheme_names().index(scheme)
+    return int(scheme)
+
+
+# --------------------------------------------------------------- pre-pass
+
+
+def ktau_rank(X: torch.Tensor, stream=None, check: bool = True) -> dict:
+    """Per-row order, dense ranks, run starts (uint16 stored in int32 views)
+    and n1, from the rank pre-pass kernel."""
+    X = _as_matrix(X)
+    m, n = X.shape
+    dev = X.device
+    perm = torch.empty((m, n), dtype=torch.int16, device=dev)
+    rank = torch.empty((m, n), dtype=torch.int16, device=dev)
+    rstart = torch.empty((m, n), dtype=torch.int16, device=dev)
+    n1 = torch.empty(m, dtype=torch.int64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(lib().ktau_rank(_ptr(X), m, n, _ptr(perm), _ptr(rank), _ptr(rstart), _ptr(n1),
+                           _ptr(status), _stream(stream)), "ktau_rank")
+    if check:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        st = int(status.item())
+        if st != 0:
+            raise KtauError(st, "ktau_rank")
+    u16 = lambda t: t.to(torch.int32) & 0xFFFF  # noqa: E731
+    return {"perm": u16(perm), "rank": u16(rank), "rstart": u16(rstart), "n1": n1}
+
+
+# -------------------------------------------------------------- all-pairs
+
+
+def ktau_allpairs_workspace_size(m: int, n: int) -> int:
+    return int(lib().ktau_allpairs_workspace_size(m, n))
+
+
+def alloc_outputs(P: int, m: int, device, tau_a: bool = False, counts: bool = True) -> dict:
+    out = {"tau_b": torch.empty(P, dtype=torch.float64, device=device),
+           "n1": torch.empty(m, dtype=torch.int64, device=device)}
+    if counts:
+        for k in ("nc", "nd", "n3"):
+            out[k] = torch.empty(P, dtype=torch.int64, device=device)
+    if tau_a:
+        out["tau_a"] = torch.empty(P, dtype=torch.float64, device=device)
+    return out
+
+
+def _pair_out(out: dict) -> _PairOut:
+    return _PairOut(*(ctypes.c_void_p(out[k].data_ptr()) if out.get(k) is not None else None
+                      for k in ("nc", "nd", "n3", "tau_b", "tau_a", "n1")))
+
+
+def alloc_workspace(m: int, n: int, device) -> torch.Tensor:
+    size = ktau_allpairs_workspace_size(m, n)
+    if size == 0:
+        raise KtauError(KTAU_EINVAL if n <= KTAU_MAX_N else KTAU_ERANGE, "workspace size")
+    return torch.empty(size, dtype=torch.uint8, device=device)
+
+
+def ktau_allpairs_ex(X: torch.Tensor, J_begin: int, J_end: int, out: dict, workspace: torch.Tensor,
+                     scheme=None, q: int = 0, stream=None) -> None:
+    X = _as_matrix(X)
+    m, n = X.shape
+    _check(lib().ktau_allpairs_ex(_ptr(X), m, n, J_begin, J_end, _pair_out(out), _ptr(workspace),
+                                  workspace.numel(), scheme_id(scheme), int(q), _stream(stream)),
+           "ktau_allpairs_ex")
+
+
+def ktau_status(workspace: torch.Tensor, stream=None) -> int:
+    return int(lib().ktau_status(_ptr(workspace), _stream(stream)))
+
+
+def ktau_allpairs(X: torch.Tensor, out: dict | None = None, workspace: torch.Tensor | None = None,
+                  scheme=None, q: int = 0, tau_a: bool = False, stream=None,
+                  check: bool = True) -> dict:
+    """All strict pairs of the rows of X (a CUDA float32 m x n tensor).
+
+    Returns a dict of device tensors: nc, nd, n3 (int64), tau_b (and tau_a)
+    (float64) indexed by strict job id, and n1 (int64, per row).  With
+    check=True the stream is synchronised and a device-side error (NaN input)
+    raises KtauError."""
+    X = _as_matrix(X)
+    m, n = X.shape
+    P = m * (m - 1) // 2
+    if out is None:
+        out = alloc_outputs(P, m, X.device, tau_a=tau_a)
+    if workspace is None:
+        workspace = alloc_workspace(m, n, X.device)
+    if scheme is None and q == 0:
+        _check(lib().ktau_allpairs(_ptr(X), m, n, _pair_out(out), _ptr(workspace),
+                                   workspace.numel(), _stream(stream)), "ktau_allpairs")
+    else:
+        ktau_allpairs_ex(X, -1, -1, out, workspace, scheme, q, stream)
+    if check:
+        st = ktau_status(workspace, stream)
+        if st != KTAU_OK:
+            raise KtauError(st, "ktau_allpairs")
+    return out
+
+
+def ktau_allpairs_range(X: torch.Tensor, J_begin: int, J_end: int, out: dict | None = None,
+                        workspace: torch.Tensor | None = None, scheme=None, stream=None,
+                        check: bool = True) -> dict:
+    X = _as_matrix(X)
+    m, n = X.shape
+    cnt = max(0, J_end - J_begin)
+    if out is None:
+        out = alloc_outputs(cnt, m, X.device)
+    if workspace is None:
+        workspace = alloc_workspace(m, n, X.device)
+    if scheme is None:
+        _check(lib().ktau_allpairs_range(_ptr(X), m, n, J_begin, J_end, _pair_out(out),
+                                         _ptr(workspace), workspace.numel(), _stream(stream)),
+               "ktau_allpairs_range")
+    else:
+        ktau_allpairs_ex(X, J_begin, J_end, out, workspace, scheme, 0, stream)
+    if check:
+        st = ktau_status(workspace, stream)
+        if st != KTAU_OK:
+            raise KtauError(st, "ktau_allpairs_range")
+    return out

@@ -1,0 +1,88 @@
+"""The C-ABI library loads, exports every symbol its headers declare, and
+rejects bad arguments on the host before anything reaches a device."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_1704_03767_amd import ktau as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(ktau_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared_functions()
+    assert "ktau_allpairs" in names and "ktau_job_to_pair" in names
+    lib = ctypes.CDLL(K.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert K.status_string(code) not in ("", "unknown status")
+    assert K.status_string(-99) == "unknown status"
+
+
+def _out():
+    return K._PairOut(None, None, None, None, None, None)
+
+
+def test_host_side_argument_errors():
+    L = K.lib()
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced: rejected first
+    ws = ctypes.c_void_p(0x100000)
+    assert L.ktau_allpairs(None, 10, 10, _out(), ws, 1 << 20, None) == K.KTAU_EINVAL
+    assert L.ktau_allpairs(fake, 1, 10, _out(), ws, 1 << 20, None) == K.KTAU_EINVAL
+    assert L.ktau_allpairs(fake, 10, 1, _out(), ws, 1 << 20, None) == K.KTAU_EINVAL
+    assert L.ktau_allpairs(fake, 10, K.KTAU_MAX_N + 1, _out(), ws, 1 << 30, None) == K.KTAU_ERANGE
+    assert L.ktau_allpairs(fake, 10, 10, _out(), ws, 16, None) == K.KTAU_ENOMEM
+    assert L.ktau_allpairs(fake, 10, 10, _out(), ctypes.c_void_p(0x100008), 1 << 20,
+                           None) == K.KTAU_EINVAL            # misaligned workspace
+    assert L.ktau_allpairs_range(fake, 10, 10, -1, 5, _out(), ws, 1 << 20, None) == K.KTAU_ERANGE
+    assert L.ktau_allpairs_range(fake, 10, 10, 5, 46, _out(), ws, 1 << 20, None) == K.KTAU_ERANGE
+    assert L.ktau_allpairs_range(fake, 10, 10, 6, 5, _out(), ws, 1 << 20, None) == K.KTAU_ERANGE
+    assert L.ktau_allpairs_ex(fake, 300, 300, -1, -1, _out(), ws, 1 << 30, 0, 0,
+                              None) == K.KTAU_EINVAL       # wave_k2 holds n <= 128
+    assert L.ktau_allpairs_ex(fake, 30, 30, -1, -1, _out(), ws, 1 << 30, 99, 0,
+                              None) == K.KTAU_EINVAL
+    assert L.ktau_allpairs_ex(fake, 30, 30, -1, -1, _out(), ws, 1 << 30, -1, 65,
+                              None) == K.KTAU_EINVAL
+    assert L.ktau_allpairs_workspace_size(1, 10) == 0
+    assert L.ktau_allpairs_workspace_size(10, K.KTAU_MAX_N + 1) == 0
+    assert L.ktau_rank(None, 3, 3, None, None, None, None, fake, None) == K.KTAU_EINVAL
+    assert L.ktau_rank(fake, 3, K.KTAU_MAX_N + 1, None, None, None, None, fake,
+                       None) == K.KTAU_ERANGE
+    assert L.ktau_pair_to_job(10, 3, 3) == -1
+    assert L.ktau_pair_to_job(10, 4, 3) == -1
+    assert L.ktau_pair_to_job(10, 3, 10) == -1
+
+
+def test_scheme_table():
+    names = K.ktau_scheme_names()
+    assert len(names) == K.lib().ktau_scheme_count()
+    caps = [K.ktau_scheme_capacity(i) for i in range(len(names))]
+    assert max(caps) >= K.KTAU_MAX_N
+    for n in (2, 64, 128, 129, 512, 1024, 1025, 4096):
+        s = K.ktau_default_scheme(n)
+        assert caps[s] >= n
+    assert K.ktau_scheme_capacity(-1) == -1
+
+
+def test_workspace_size_grows_with_shape():
+    a = K.ktau_allpairs_workspace_size(64, 128)
+    b = K.ktau_allpairs_workspace_size(16384, 1024)
+    assert 0 < a < b
+    assert b >= 3 * 16384 * 1024 * 2

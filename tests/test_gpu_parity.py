@@ -1,0 +1,243 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Bar: n_c, n_d, n3, n1 bit-exact; tau_B within 1e-15 absolute (identical
+integers and the same IEEE formula, so it is expected to be equal); rank
+pre-pass outputs bit-exact.  Full-size workloads are checked on seeded samples
+of pairs the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1704_03767_amd import ktau as K
+from paper_1704_03767_amd import synth
+
+pytestmark = pytest.mark.gpu
+TAU_TOL = 1e-15
+
+
+def _np(d):
+    return {k: v.cpu().numpy() for k, v in d.items() if v is not None}
+
+
+def _gpu_allpairs(X, **kw):
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    return _np(K.ktau_allpairs(Xd, tau_a=True, **kw))
+
+
+def _assert_tau(got, want, what="tau_b"):
+    assert np.array_equal(np.isnan(got), np.isnan(want)), what
+    ok = ~np.isnan(want)
+    if ok.any():
+        err = np.abs(got[ok] - want[ok]).max()
+        assert err <= TAU_TOL, (what, err)
+
+
+def _assert_same(got, want, slots=None):
+    sel = (lambda a: a) if slots is None else (lambda a: a[slots])
+    for k in ("nc", "nd", "n3"):
+        g, w = sel(got[k]), want[k]
+        if not np.array_equal(g, w):
+            bad = np.nonzero(g != w)[0]
+            raise AssertionError(f"{k} differs at {bad.size} slots, first {bad[:5]}: "
+                                 f"got {g[bad[:5]]} want {w[bad[:5]]}")
+    _assert_tau(sel(got["tau_b"]), want["tau_b"])
+    if "tau_a" in want and "tau_a" in got:
+        _assert_tau(sel(got["tau_a"]), want["tau_a"], "tau_a")
+
+
+def _check_full(X, **kw):
+    got = _gpu_allpairs(X, **kw)
+    want = oracle.allpairs(X, "gse")
+    _assert_same(got, want)
+    assert np.array_equal(got["n1"], want["n1"])
+    return got
+
+
+# ------------------------------------------------------------- rank pre-pass
+
+
+def _oracle_rstart(order, rank):
+    srt = np.take_along_axis(rank, order, axis=1)          # dense rank at sorted position
+    out = np.empty_like(srt)
+    for r in range(srt.shape[0]):
+        out[r] = np.searchsorted(srt[r], srt[r], side="left")
+    return out
+
+
+@pytest.mark.parametrize("shape_seed", [(64, 128, 1), (33, 1000, 2), (17, 4096, 3), (5, 2, 4),
+                                        (9, 65, 5)])
+def test_prepass_matches_oracle(shape_seed):
+    m, n, seed = shape_seed
+    rng = np.random.default_rng(seed)
+    X = np.round(rng.standard_normal((m, n)), 1).astype(np.float32)
+    X[0, : n // 2] = -0.0
+    X[0, n // 2:] = 0.0
+    X[1] = 3.0                                             # constant row
+    if m > 3:
+        X[2] = np.float32(np.inf)
+        X[2, ::3] = -np.inf
+    got = K.ktau_rank(torch.from_numpy(X).cuda())
+    want = oracle.rank_rows(X)
+    assert np.array_equal(got["perm"].cpu().numpy(), want["order"])
+    assert np.array_equal(got["rank"].cpu().numpy(), want["rank"])
+    assert np.array_equal(got["n1"].cpu().numpy(), want["n1"])
+    assert np.array_equal(got["rstart"].cpu().numpy(), _oracle_rstart(want["order"], want["rank"]))
+
+
+# ------------------------------------------------------------ small workload
+
+
+@pytest.mark.parametrize("scheme", list(range(7)))
+def test_small_workload_every_scheme(scheme):
+    X = synth.config_matrix(1)                              # 64 x 128, ties from rounding
+    _check_full(X, scheme=scheme)
+
+
+@pytest.mark.parametrize("q", [1, 3, 8, 16, 64])
+def test_small_workload_tile_edges(q):
+    X = synth.config_matrix(1)
+    _check_full(X, q=q)
+
+
+def test_small_workload_twice_is_identical():
+    X = synth.config_matrix(1)
+    a = _gpu_allpairs(X)
+    b = _gpu_allpairs(X)
+    for k in ("nc", "nd", "n3", "tau_b", "n1"):
+        assert np.array_equal(a[k], b[k], equal_nan=True)
+
+
+# ------------------------------------------------------------ edge shapes
+
+
+EDGE_N = [2, 3, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025,
+          2047, 2048, 2049, 4095, 4096]
+
+
+def _edge_matrix(m, n, seed):
+    rng = np.random.default_rng(seed)
+    X = np.round(rng.standard_normal((m, n)), 1).astype(np.float32)
+    X[0] = 1.0                                               # constant
+    X[1] = rng.integers(0, 2, n).astype(np.float32)          # binary: very many ties
+    X[2] = rng.permutation(n).astype(np.float32)             # no ties
+    X[3] = -X[2]
+    X[4] = X[2]
+    X[5] = np.where(rng.random(n) < 0.5, -0.0, 0.0).astype(np.float32)
+    X[5, :: 7] = 1.0
+    X[6] = rng.integers(0, 3, n).astype(np.float32)
+    return X
+
+
+@pytest.mark.parametrize("n", EDGE_N)
+def test_edge_sample_counts(n):
+    m = 9
+    X = _edge_matrix(m, n, n)
+    got = _check_full(X)
+    # closed forms on the planted rows (self, negation)
+    j = K.ktau_pair_to_job(m, 2, 4)
+    assert got["tau_b"][j] == 1.0
+    j = K.ktau_pair_to_job(m, 2, 3)
+    assert got["tau_b"][j] == -1.0
+    for x in range(1, m):
+        assert np.isnan(got["tau_b"][K.ktau_pair_to_job(m, 0, x)])
+
+
+@pytest.mark.parametrize("n", [100, 700, 1500, 3000])
+def test_block_schemes_on_edges(n):
+    X = _edge_matrix(9, n, 7 + n)
+    for scheme in range(7):
+        if K.ktau_scheme_capacity(scheme) >= n:
+            _check_full(X, scheme=scheme)
+
+
+@pytest.mark.parametrize("m", [2, 3, 7, 8, 9, 17])
+def test_edge_row_counts(m):
+    rng = np.random.default_rng(m)
+    X = np.round(rng.standard_normal((m, 300)), 1).astype(np.float32)
+    _check_full(X)
+    _check_full(X, q=4)
+
+
+def test_heavy_tie_paths():
+    # Pairs where both rows carry ties: a few (direct in-run count) and very
+    # many (the literal (u, v) sort), at several n.
+    rng = np.random.default_rng(21)
+    for n in (128, 300, 1024, 2500):
+        rows = []
+        for levels in (2, 3, 4, 8, 30, 200):
+            rows.append(rng.integers(0, levels, n).astype(np.float32))
+        rows.append(np.where(rng.random(n) < 0.9, 0.0, rng.standard_normal(n)).astype(np.float32))
+        rows.append(np.where(rng.random(n) < 0.05, 0.0, rng.standard_normal(n)).astype(np.float32))
+        X = np.stack(rows)
+        _check_full(X)
+
+
+# ------------------------------------------------------------ job sub-ranges
+
+
+def test_ranges_equal_full_slices():
+    X = synth.config_matrix(1)
+    m, n = X.shape
+    Xd = torch.from_numpy(X).cuda()
+    full = _np(K.ktau_allpairs(Xd))
+    P = m * (m - 1) // 2
+    for a, b in [(0, P), (0, 1), (5, 6), (100, 1000), (P - 7, P), (1000, 1000)]:
+        part = _np(K.ktau_allpairs_range(Xd, a, b))
+        for k in ("nc", "nd", "n3", "tau_b"):
+            assert np.array_equal(part[k], full[k][a:b], equal_nan=True), (a, b, k)
+    for scheme in (0, 4):
+        part = _np(K.ktau_allpairs_range(Xd, 7, 1500, scheme=scheme))
+        for k in ("nc", "nd", "n3", "tau_b"):
+            assert np.array_equal(part[k], full[k][7:1500], equal_nan=True)
+
+
+# ------------------------------------------------------------ errors
+
+
+def test_nan_input_is_reported():
+    X = synth.config_matrix(1).copy()
+    X[10, 20] = np.nan
+    with pytest.raises(K.KtauError) as e:
+        _gpu_allpairs(X)
+    assert e.value.status == K.KTAU_ENAN
+    # the workspace status is cleared and the next call succeeds
+    _check_full(synth.config_matrix(1))
+
+
+# ------------------------------------------------------------ full-size workloads
+
+
+def _sampled(cfg, count, seed):
+    X = synth.config_matrix(cfg)
+    m, n = X.shape
+    Xd = torch.from_numpy(X).cuda()
+    got = _np(K.ktau_allpairs(Xd))
+    del Xd
+    P = m * (m - 1) // 2
+    rng = np.random.default_rng(seed)
+    J = np.unique(np.concatenate([rng.integers(0, P, count), [0, P - 1]]))
+    yx = np.array([K.ktau_job_to_pair(m, int(j)) for j in J])
+    want = oracle.pairs(X, yx[:, 0], yx[:, 1], "gse")
+    _assert_same(got, want, slots=J)
+    assert np.array_equal(got["n1"], oracle.rank_rows(X)["n1"])
+    # properties at every pair: partition identity and |tau| <= 1
+    n0 = n * (n - 1) // 2
+    n1 = got["n1"]
+    ys, xs = yx[:, 0], yx[:, 1]
+    assert np.all(got["nc"][J] + got["nd"][J] + n1[ys] + n1[xs] - got["n3"][J] == n0)
+    tb = got["tau_b"]
+    assert np.all(np.abs(tb[~np.isnan(tb)]) <= 1.0)
+    assert (got["nd"] >= 0).all() and (got["nc"] >= 0).all() and (got["n3"] >= 0).all()
+    return got
+
+
+@pytest.mark.slow
+def test_medium_workload_sampled():
+    _sampled(2, 20000, 22)
+
+
+@pytest.mark.slow
+def test_gene_expression_scale_sampled():
+    _sampled(3, 20000, 33)
