@@ -128,6 +128,19 @@ int ktau_allpairs_range(const float* X_dev, int64_t m, int64_t n,
                         int64_t J_begin, int64_t J_end, ktau_pair_out out,
                         void* workspace_dev, size_t ws_bytes, void* stream);
 
+/* The two halves of ktau_allpairs, for callers that rank once and then make
+ * several passes over job sub-ranges (Sec. 4.3) or time the halves apart.
+ * ktau_prepare clears the workspace status and runs the rank pre-pass of X
+ * into the workspace (writing out_n1_dev[m] too if it is not NULL).
+ * ktau_pairs computes jobs [J_begin, J_end) (J_begin < 0: all jobs, in tile
+ * order) from a workspace prepared for the same (m, n); scheme < 0 and q <= 0
+ * pick the defaults. */
+int ktau_prepare(const float* X_dev, int64_t m, int64_t n, int64_t* out_n1_dev,
+                 void* workspace_dev, size_t ws_bytes, void* stream);
+int ktau_pairs(int64_t m, int64_t n, int64_t J_begin, int64_t J_end,
+               ktau_pair_out out, void* workspace_dev, size_t ws_bytes,
+               int scheme, int q, void* stream);
+
 /* Waits for `stream`, then returns the status latched in a workspace by the
  * last call that used it (KTAU_ENAN if the input held a NaN, else KTAU_OK),
  * and clears it. */

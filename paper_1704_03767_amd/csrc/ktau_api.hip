@@ -1,34 +1,34 @@
-// C ABI of libktau: argument checks, workspace layout and launches for the
-// job mapper, the rank pre-pass and the plain all-pairs calls.
+// C ABI of libktau, plain path: argument checks, workspace layout, and the
+// launches for the job mapper, the rank pre-pass and the all-pairs calls.
 #include <stdlib.h>
 #include <string.h>
 
 #include "ktau_internal.h"
 
 namespace ktau {
+
 namespace {
-
-__global__ void clear_status_kernel(int32_t* status) { *status = 0; }
-
-struct WsLayout {
-  size_t perm, rank, rstart, n1, total;
-  int64_t ld;
-};
+__global__ void clear_words_kernel(int32_t* p, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
+}
+}  // namespace
 
 WsLayout ws_layout(int64_t m, int64_t n) {
   WsLayout L;
   L.ld = round_up(n, kRowAlign);
-  size_t rowbytes = (size_t)m * (size_t)L.ld * sizeof(uint16_t);
-  size_t off = kWsHeader;
-  L.perm = off;
-  off = (size_t)round_up((int64_t)(off + rowbytes), (int64_t)kAlign);
-  L.rank = off;
-  off = (size_t)round_up((int64_t)(off + rowbytes), (int64_t)kAlign);
-  L.rstart = off;
-  off = (size_t)round_up((int64_t)(off + rowbytes), (int64_t)kAlign);
-  L.n1 = off;
-  off = (size_t)round_up((int64_t)(off + (size_t)m * sizeof(int64_t)), (int64_t)kAlign);
-  L.total = off;
+  const int64_t rowbytes = m * L.ld * (int64_t)sizeof(uint16_t);
+  int64_t off = (int64_t)kWsHeader;
+  L.perm = (size_t)off;
+  off = round_up(off + rowbytes, (int64_t)kAlign);
+  L.rank = (size_t)off;
+  off = round_up(off + rowbytes, (int64_t)kAlign);
+  L.rstart = (size_t)off;
+  off = round_up(off + rowbytes, (int64_t)kAlign);
+  L.n1 = (size_t)off;
+  off = round_up(off + m * (int64_t)sizeof(int64_t), (int64_t)kAlign);
+  L.heavy = (size_t)off;
+  off = round_up(off + m * (int64_t)sizeof(int32_t), (int64_t)kAlign);
+  L.total = (size_t)off;
   return L;
 }
 
@@ -44,35 +44,77 @@ int env_int(const char* name, int dflt) {
   return atoi(s);
 }
 
-}  // namespace
-
-// Shared by the batch and server units.
-int run_prepass_into(const float* X, int64_t m, int64_t n, void* ws, RankView& rv,
-                     int64_t* n1_out, int32_t*& status, hipStream_t s) {
-  WsLayout L = ws_layout(m, n);
+MatDesc matdesc(void* ws, int64_t m, int64_t n, const ktau_pair_out& out, int scheme, int q,
+                int64_t J_begin, int64_t J_end, int32_t* status) {
+  const WsLayout L = ws_layout(m, n);
   char* base = (char*)ws;
-  status = (int32_t*)base;
-  uint16_t* perm = (uint16_t*)(base + L.perm);
-  uint16_t* rank = (uint16_t*)(base + L.rank);
-  uint16_t* rstart = (uint16_t*)(base + L.rstart);
-  int64_t* n1 = (int64_t*)(base + L.n1);
-  if (launch_prepass(X, m, n, perm, rank, rstart, L.ld, n1, n1_out, status, s) != hipSuccess)
+  MatDesc d;
+  memset(&d, 0, sizeof(d));
+  d.rv.perm = (const uint16_t*)(base + L.perm);
+  d.rv.rank = (const uint16_t*)(base + L.rank);
+  d.rv.rstart = (const uint16_t*)(base + L.rstart);
+  d.rv.n1 = (const int64_t*)(base + L.n1);
+  d.rv.ld = L.ld;
+  d.out = PairOut{out.nc, out.nd, out.n3, out.tau_b, out.tau_a};
+  d.status = status ? status : (const int32_t*)base;
+  d.heavy_count = (int32_t*)(base + 4);
+  d.heavy = (int32_t*)(base + L.heavy);
+  d.m = m;
+  d.n = (int32_t)n;
+  d.scheme = scheme;
+  d.q = q;
+  d.w = (m + q - 1) / q;
+  d.n_units = d.w * (d.w + 1) / 2;
+  d.unit_begin = 0;
+  d.J_begin = J_begin;
+  d.J_end = J_end;
+  return d;
+}
+
+int prepass_ws(const float* X, int64_t m, int64_t n, void* ws, int64_t* n1_out, int32_t* status,
+               hipStream_t s) {
+  const WsLayout L = ws_layout(m, n);
+  char* base = (char*)ws;
+  if (launch_prepass(X, m, n, (uint16_t*)(base + L.perm), (uint16_t*)(base + L.rank),
+                     (uint16_t*)(base + L.rstart), L.ld, (int64_t*)(base + L.n1), n1_out,
+                     status ? status : (int32_t*)base, s) != hipSuccess)
     return KTAU_EDEVICE;
-  rv.perm = perm;
-  rv.rank = rank;
-  rv.rstart = rstart;
-  rv.n1 = n1;
-  rv.ld = L.ld;
   return KTAU_OK;
 }
 
-size_t workspace_bytes(int64_t m, int64_t n) { return ws_layout(m, n).total; }
-
-int clear_status(int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, s, status);
+int clear_words(int32_t* p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(64), 0, s, p, count);
   return hipGetLastError() == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
 }
 
+namespace {
+
+int check_ws(int64_t m, int64_t n, const void* ws, size_t ws_bytes) {
+  const int rc = check_shape(m, n);
+  if (rc != KTAU_OK) return rc;
+  if (!ws || ((uintptr_t)ws) % kAlign != 0) return KTAU_EINVAL;
+  if (ws_bytes < ws_layout(m, n).total) return KTAU_ENOMEM;
+  return KTAU_OK;
+}
+
+// Validates a job range and the launch options; J_begin < 0 means all jobs.
+int check_pairs(int64_t m, int64_t n, int64_t& J_begin, int64_t& J_end, int& scheme, int& q,
+                bool& full) {
+  const int64_t P = m * (m - 1) / 2;
+  full = J_begin < 0;
+  if (full) {
+    J_begin = 0;
+    J_end = P;
+  }
+  if (J_begin > J_end || J_end > P) return KTAU_ERANGE;
+  if (scheme < 0) scheme = env_int("KTAU_FORCE_SCHEME", default_scheme(n));
+  if (scheme < 0 || scheme >= kNumSchemes || scheme_capacity(scheme) < n) return KTAU_EINVAL;
+  if (q <= 0) q = env_int("KTAU_TILE_Q", 8);
+  if (q < 1 || q > 64) return KTAU_EINVAL;
+  return KTAU_OK;
+}
+
+}  // namespace
 }  // namespace ktau
 
 using namespace ktau;
@@ -117,14 +159,14 @@ int ktau_rank(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* ra
               uint16_t* rstart, int64_t* n1, int32_t* status, void* stream) {
   if (!X || !status || m < 1 || n < 1 || m > (int64_t)0x7fffffff) return KTAU_EINVAL;
   if (n > KTAU_MAX_N) return KTAU_ERANGE;
-  hipError_t e = launch_prepass(X, m, n, perm, rank, rstart, n, nullptr, n1, status,
-                                (hipStream_t)stream);
+  const hipError_t e = launch_prepass(X, m, n, perm, rank, rstart, n, nullptr, n1, status,
+                                      (hipStream_t)stream);
   return e == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
 }
 
 size_t ktau_allpairs_workspace_size(int64_t m, int64_t n) {
   if (check_shape(m, n) != KTAU_OK) return 0;
-  return workspace_bytes(m, n);
+  return ws_layout(m, n).total;
 }
 
 int ktau_scheme_count(void) { return kNumSchemes; }
@@ -134,40 +176,40 @@ int64_t ktau_scheme_capacity(int scheme) {
 }
 int ktau_default_scheme(int64_t n) { return default_scheme(n); }
 
+int ktau_prepare(const float* X, int64_t m, int64_t n, int64_t* out_n1, void* ws,
+                 size_t ws_bytes, void* stream) {
+  int rc = check_ws(m, n, ws, ws_bytes);
+  if (rc != KTAU_OK) return rc;
+  if (!X) return KTAU_EINVAL;
+  const hipStream_t s = (hipStream_t)stream;
+  if (clear_words((int32_t*)ws, 2, s) != KTAU_OK) return KTAU_EDEVICE;
+  return prepass_ws(X, m, n, ws, out_n1, nullptr, s);
+}
+
+int ktau_pairs(int64_t m, int64_t n, int64_t J_begin, int64_t J_end, ktau_pair_out out,
+               void* ws, size_t ws_bytes, int scheme, int q, void* stream) {
+  int rc = check_ws(m, n, ws, ws_bytes);
+  if (rc != KTAU_OK) return rc;
+  bool full;
+  rc = check_pairs(m, n, J_begin, J_end, scheme, q, full);
+  if (rc != KTAU_OK) return rc;
+  const MatDesc d = matdesc(ws, m, n, out, scheme, q, J_begin, J_end, nullptr);
+  const hipError_t e = launch_pairs_plain(d, full, (hipStream_t)stream);
+  return e == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
+}
+
 int ktau_allpairs_ex(const float* X, int64_t m, int64_t n, int64_t J_begin, int64_t J_end,
                      ktau_pair_out out, void* ws, size_t ws_bytes, int scheme, int q,
                      void* stream) {
-  int rc = check_shape(m, n);
+  int rc = check_ws(m, n, ws, ws_bytes);
   if (rc != KTAU_OK) return rc;
-  if (!X || !ws) return KTAU_EINVAL;
-  if (((uintptr_t)ws) % kAlign != 0) return KTAU_EINVAL;
-  const int64_t P = m * (m - 1) / 2;
-  const bool full = J_begin < 0;
-  if (full) {
-    J_begin = 0;
-    J_end = P;
-  }
-  if (J_begin > J_end || J_end > P) return KTAU_ERANGE;
-  if (ws_bytes < workspace_bytes(m, n)) return KTAU_ENOMEM;
-  if (scheme < 0) scheme = env_int("KTAU_FORCE_SCHEME", default_scheme(n));
-  if (scheme < 0 || scheme >= kNumSchemes || scheme_capacity(scheme) < n) return KTAU_EINVAL;
-  if (q <= 0) q = env_int("KTAU_TILE_Q", 8);
-  if (q < 1 || q > 64) return KTAU_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  RankView rv;
-  int32_t* status = nullptr;
-  if (clear_status((int32_t*)ws, s) != KTAU_OK) return KTAU_EDEVICE;
-  rc = run_prepass_into(X, m, n, ws, rv, out.n1, status, s);
+  if (!X) return KTAU_EINVAL;
+  bool full;
+  rc = check_pairs(m, n, J_begin, J_end, scheme, q, full);
   if (rc != KTAU_OK) return rc;
-  PairOut po{out.nc, out.nd, out.n3, out.tau_b, out.tau_a};
-  hipError_t e;
-  if (full) {
-    const int64_t w = (m + q - 1) / q;
-    e = launch_pairs_tiles(scheme, rv, m, (int)n, q, w, 0, w * (w + 1) / 2, po, status, s);
-  } else {
-    e = launch_pairs_jobs(scheme, rv, m, (int)n, J_begin, J_end, po, status, s);
-  }
-  return e == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
+  rc = ktau_prepare(X, m, n, out.n1, ws, ws_bytes, stream);
+  if (rc != KTAU_OK) return rc;
+  return ktau_pairs(m, n, full ? -1 : J_begin, J_end, out, ws, ws_bytes, scheme, q, stream);
 }
 
 int ktau_allpairs(const float* X, int64_t m, int64_t n, ktau_pair_out out, void* ws,
@@ -187,7 +229,7 @@ int ktau_status(void* ws, void* stream) {
   int32_t st = 0;
   if (hipMemcpy(&st, ws, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return KTAU_EDEVICE;
   if (st != 0) {
-    int32_t zero = 0;
+    const int32_t zero = 0;
     if (hipMemcpy(ws, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
       return KTAU_EDEVICE;
   }

@@ -1,0 +1,266 @@
+// Register-resident inversion count for the pair kernels (the Step 3 count of
+// Sec. 3.2, Algorithm 2, computed with a different merge schedule).
+//
+// A group of G lanes holds N = G*K keys, K per lane, lane-blocked (element
+// e = lane*K + r).  Keys are 16-bit dense ranks, packed two per VGPR: VGPR j
+// holds elements r = j (low half) and r = j + K/2 (high half).
+//
+// The sort is a bitonic network, level L merging sorted blocks of s = 2^L
+// into blocks of 2s.  Exactly as in Algorithm 2, the count of a level is, over
+// every block, the number of (left-half element, right-half element) pairs
+// whose left element is strictly larger.  It is read off the merged block
+// without comparing pairs: before the level every key is tagged in its least
+// significant bit with the half it comes from (key' = 2*rank + tag), so the
+// network sorts equal ranks left-half first; a right-half element that lands
+// at ascending position p of its merged block, as the j-th of its half, has
+// exactly p - j left elements at or below it.  Summing over the block,
+//     inversions = s*s + s(s-1)/2 - (sum of positions of right-half elements),
+// and one v_dot2_u32_u16 per VGPR accumulates that position sum.
+//
+// Bitonic merging needs every other block sorted descending.  Instead of
+// selecting min or max per lane, keys of a descending block are stored
+// complemented, so every comparator of every stage keeps the minimum at the
+// lower position; a complemented block's physical position q is ascending
+// position 2s-1-q, which flips the sign of its term (see level_count).
+//
+// Partners at distance d:  d < K/2 -> another VGPR of the same lane (one
+// v_pk_min_u16 + one v_pk_max_u16 for two comparators);  d = K/2 -> the two
+// halves of one VGPR;  d >= K: another lane.  Lane distances 1..8 use
+// ds_swizzle; 16 and 32 use v_permlane16_swap / v_permlane32_swap, which
+// exchange half the lanes of two VGPRs so that the comparison becomes a plain
+// min/max between the two registers, and swap back; lane distances >= 64
+// (a 256-lane group) go through LDS.
+#pragma once
+
+#include "ktau_internal.h"
+
+namespace ktau {
+namespace bitonic {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bits(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ u16x2 vec(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ u16x2 pmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ u16x2 pmax(u16x2 a, u16x2 b) { return __builtin_elementwise_max(a, b); }
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+// Value of lane ^ M (M < 32) by ds_swizzle in bit-mask mode.
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  static_assert(M > 0 && M < 32, "swizzle reaches 32 lanes");
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (M << 10) | 0x1F);
+}
+
+template <int K, int G>
+struct Net {
+  static constexpr int KV = K / 2;            // VGPRs per lane
+  static constexpr int LOGK = ilog2(K);
+  static constexpr int LOGKV = ilog2(KV);
+  static constexpr int LOGG = ilog2(G);
+  static constexpr int LOGN = LOGK + LOGG;
+  static constexpr int N = K * G;
+  static_assert(K >= 2 && (K & (K - 1)) == 0, "K is a power of two");
+  static_assert(G == 64 || G == 256, "a wave or a 256-lane workgroup");
+
+  // Bit b of element (lane, j, h).
+  static __device__ __forceinline__ uint32_t ebit(int lane, int j, int h, int b) {
+    const uint32_t e = ((uint32_t)lane << LOGK) | ((uint32_t)h << LOGKV) | (uint32_t)j;
+    return (e >> b) & 1u;
+  }
+  static __device__ __forceinline__ uint32_t half_mask(uint32_t lo, uint32_t hi) {
+    return (lo ? 0xFFFFu : 0u) | (hi ? 0xFFFF0000u : 0u);
+  }
+
+  // One comparator stage on element bit k (partners e and e ^ 2^k).
+  template <int k>
+  static __device__ __forceinline__ void stage(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
+    if constexpr (k < LOGKV) {
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        if ((j >> k) & 1) continue;
+        const int p = j | (1 << k);
+        const u16x2 a = v[j], b = v[p];
+        v[j] = pmin(a, b);
+        v[p] = pmax(a, b);
+      }
+    } else if constexpr (k == LOGKV) {
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        const u16x2 t = __builtin_shufflevector(v[j], v[j], 1, 0);
+        const u16x2 mn = pmin(v[j], t), mx = pmax(v[j], t);
+        v[j] = __builtin_shufflevector(mn, mx, 0, 3);
+      }
+    } else {
+      constexpr int lb = k - LOGK;            // lane bit
+      if constexpr (lb < 4) {
+        const bool lower = ((lane >> lb) & 1) == 0;
+#pragma unroll
+        for (int j = 0; j < KV; ++j) {
+          const u16x2 p = vec(lane_xor<(1 << lb)>(bits(v[j])));
+          const u16x2 mn = pmin(v[j], p), mx = pmax(v[j], p);
+          v[j] = lower ? mn : mx;
+        }
+      } else if constexpr (lb == 4 || lb == 5) {
+        if constexpr (KV >= 2) {
+#pragma unroll
+          for (int j = 0; j < KV; j += 2) {
+            uint32_t a = bits(v[j]), b = bits(v[j + 1]);
+            if constexpr (lb == 4) {
+              auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+              a = s[0];
+              b = s[1];
+            } else {
+              auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+              a = s[0];
+              b = s[1];
+            }
+            const u16x2 mn = pmin(vec(a), vec(b)), mx = pmax(vec(a), vec(b));
+            a = bits(mn);
+            b = bits(mx);
+            if constexpr (lb == 4) {
+              auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+              v[j] = vec(s[0]);
+              v[j + 1] = vec(s[1]);
+            } else {
+              auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+              v[j] = vec(s[0]);
+              v[j + 1] = vec(s[1]);
+            }
+          }
+        } else {
+          // a single VGPR: exchange with itself, keep the partner's copy
+          const bool lower = ((lane >> lb) & 1) == 0;
+          uint32_t a = bits(v[0]);
+          uint32_t part;
+          if constexpr (lb == 4) {
+            auto s = __builtin_amdgcn_permlane16_swap(a, a, false, false);
+            part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
+          } else {
+            auto s = __builtin_amdgcn_permlane32_swap(a, a, false, false);
+            part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
+          }
+          const u16x2 mn = pmin(v[0], vec(part)), mx = pmax(v[0], vec(part));
+          v[0] = lower ? mn : mx;
+        }
+      } else {
+        // across the waves of a 256-lane group, through LDS
+        const bool lower = ((lane >> lb) & 1) == 0;
+#pragma unroll
+        for (int j = 0; j < KV; ++j) xbuf[j * G + lane] = bits(v[j]);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KV; ++j) {
+          const u16x2 p = vec(xbuf[j * G + (lane ^ (1 << lb))]);
+          const u16x2 mn = pmin(v[j], p), mx = pmax(v[j], p);
+          v[j] = lower ? mn : mx;
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  template <int L, int k>
+  static __device__ __forceinline__ void stages_down(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
+    stage<k>(v, lane, xbuf);
+    if constexpr (k > 0) stages_down<L, k - 1>(v, lane, xbuf);
+  }
+
+  // Re-tag for level L (tag = bit L of e, the half of the 2s block) and
+  // re-orient (complemented iff bit L+1 of e: a descending block).  The
+  // previous level stored key' ^ orient(bit L); working the cases through,
+  //   new = (old & 0xFFFE) ^ (bit L != bit L+1 ? 0xFFFF : 0)   per half,
+  // and level 0 starts from untagged ascending keys 2*rank.
+  template <int L>
+  static __device__ __forceinline__ void retag(u16x2 (&v)[KV], int lane) {
+#pragma unroll
+    for (int j = 0; j < KV; ++j) {
+      uint32_t c;
+      if constexpr (L == 0) {
+        const uint32_t t0 = ebit(lane, j, 0, 0), t1 = ebit(lane, j, 1, 0);
+        c = (t0 | (t1 << 16)) ^ half_mask(ebit(lane, j, 0, 1), ebit(lane, j, 1, 1));
+      } else {
+        c = half_mask(ebit(lane, j, 0, L) ^ (L + 1 < LOGN ? ebit(lane, j, 0, L + 1) : 0u),
+                      ebit(lane, j, 1, L) ^ (L + 1 < LOGN ? ebit(lane, j, 1, L + 1) : 0u));
+      }
+      v[j] = vec((bits(v[j]) & 0xFFFEFFFEu) ^ c);
+    }
+  }
+
+  // Signed position sum of level L for this lane: sum over right-half
+  // elements of (+q if in a complemented block, -q otherwise), q being the
+  // physical position inside the 2s block.  Returned modulo 2^32.
+  template <int L>
+  static __device__ __forceinline__ uint32_t level_count(const u16x2 (&v)[KV], int lane) {
+    uint32_t pos = 0, neg = 0;
+    if constexpr (L + 1 < LOGK) {
+      // block inside the lane: orientation and position are per (j, half)
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        const uint32_t o0 = ebit(lane, j, 0, L + 1), o1 = ebit(lane, j, 1, L + 1);
+        const uint32_t t = (bits(v[j]) & 0x00010001u) ^ (o0 | (o1 << 16));
+        const uint32_t m2s = (2u << L) - 1u;
+        const uint32_t q0 = (uint32_t)j & m2s, q1 = ((uint32_t)(j + KV)) & m2s;
+        const uint32_t qd = (o0 ? q0 : 0u) | ((o1 ? q1 : 0u) << 16);
+        const uint32_t qa = (o0 ? 0u : q0) | ((o1 ? 0u : q1) << 16);
+        pos = __builtin_amdgcn_udot2(vec(t), vec(qd), pos, false);
+        neg = __builtin_amdgcn_udot2(vec(t), vec(qa), neg, false);
+      }
+      return pos - neg;
+    } else {
+      // the lane lies inside one block: orientation and base are per lane
+      const bool desc = (L + 1 < LOGN) ? (((lane >> (L + 1 - LOGK)) & 1) != 0) : false;
+      const uint32_t om = desc ? 0x00010001u : 0u;
+      const uint32_t base = ((uint32_t)lane & ((1u << (L + 1 - LOGK)) - 1u)) << LOGK;
+      uint32_t cnt = 0, dsum = 0;
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        const uint32_t t = (bits(v[j]) & 0x00010001u) ^ om;
+        const uint32_t qj = (uint32_t)j | ((uint32_t)(j + KV) << 16);
+        dsum = __builtin_amdgcn_udot2(vec(t), vec(qj), dsum, false);
+        cnt += t;
+      }
+      const uint32_t s = dsum + base * ((cnt & 0xFFFFu) + (cnt >> 16));
+      return desc ? s : 0u - s;
+    }
+  }
+
+  // Constant part of all levels: a level with nb >= 2 blocks of 2s adds
+  // (nb/2) * s^2 (half the blocks ascending, half descending); the top level
+  // (one ascending block) adds s^2 + s(s-1)/2.
+  static constexpr uint32_t constant_part() {
+    uint64_t c = 0;
+    for (int L = 0; L < LOGN; ++L) {
+      const uint64_t s = 1ull << L;
+      const uint64_t nb = (uint64_t)N / (2 * s);
+      c += nb >= 2 ? (nb / 2) * s * s : s * s + s * (s - 1) / 2;
+    }
+    return (uint32_t)c;
+  }
+
+  template <int L>
+  static __device__ __forceinline__ uint32_t levels(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
+    retag<L>(v, lane);
+    stages_down<L, L>(v, lane, xbuf);
+    uint32_t c = level_count<L>(v, lane);
+    if constexpr (L + 1 < LOGN) c += levels<L + 1>(v, lane, xbuf);
+    return c;
+  }
+
+  // keys: 16-bit ranks (padding = 0x7FFF).  Returns this lane's share of the
+  // group's strict inversion count (the constant part is added by lane 0).
+  static __device__ __forceinline__ uint32_t count(const uint32_t (&key)[K], int lane,
+                                                   uint32_t* xbuf) {
+    u16x2 v[KV];
+#pragma unroll
+    for (int j = 0; j < KV; ++j)
+      v[j] = vec(((key[j] & 0x7FFFu) << 1) | ((key[j + KV] & 0x7FFFu) << 17));
+    uint32_t c = levels<0>(v, lane, xbuf);
+    if (lane == 0) c += constant_part();
+    return c;
+  }
+};
+
+}  // namespace bitonic
+}  // namespace ktau

@@ -100,18 +100,31 @@ inline int64_t scheme_capacity(int s) { return (int64_t)scheme_lanes(s) * scheme
 const char* scheme_name(int s);
 int default_scheme(int64_t n);
 
-// Matrix descriptor for the persistent batched kernel.
-struct BatchDesc {
+// Comparisons the direct in-run tie count may spend on one pair (about the
+// cost of a second sort); rows whose n1 exceeds it are "heavy", and pairs of
+// two heavy rows go to the composite pass.
+__host__ __device__ inline int64_t direct_budget(int64_t n) {
+  int64_t lg = 0;
+  while ((1ll << lg) < n) ++lg;
+  return 4 * n * lg;
+}
+
+// One matrix as seen by the pair kernels.
+struct MatDesc {
   RankView rv;
   PairOut out;
+  const int32_t* status;  // device status word (non-zero: skip all work)
+  int32_t* heavy;         // [m] list of heavy rows (written by the heavy pass)
+  int32_t* heavy_count;   // device scalar
   int64_t m;
   int32_t n;
   int32_t scheme;
-  int32_t q;            // tile edge
+  int32_t q;              // tile edge
   int32_t pad;
-  int64_t w;            // tiles per side
-  int64_t unit_begin;   // first global unit id of this matrix
-  int64_t n_units;      // w (w + 1) / 2 tiles
+  int64_t w;              // tiles per side
+  int64_t n_units;        // w (w + 1) / 2 tiles
+  int64_t unit_begin;     // first global unit id of this matrix (batched)
+  int64_t J_begin, J_end; // jobs of this call; results at J - J_begin
 };
 
 // ---- launchers (stream-ordered; return hipError_t)
@@ -120,21 +133,34 @@ hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, 
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
                           int32_t* status, hipStream_t s);
 
-// Plain launch over tiles [tile_begin, tile_begin + tile_count) of matrix m.
-hipError_t launch_pairs_tiles(int scheme, const RankView& rv, int64_t m, int n, int q, int64_t w,
-                              int64_t tile_begin, int64_t tile_count, const PairOut& out,
+// Main pair kernel over all tiles (tiles = true) or over jobs
+// [J_begin, J_end), then the heavy-row pass and the composite pass.
+hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s);
+
+// Persistent launch over all units of a descriptor table, then the heavy-row
+// and composite passes of every matrix.
+hipError_t launch_pairs_batch(const MatDesc* descs_dev, int64_t count, int64_t total_units,
+                              const int64_t* unit_prefix_dev, int64_t* counter_dev, int grid,
                               const int32_t* status, hipStream_t s);
 
-// Plain launch over strict job ids [J_begin, J_end); results at J - J_begin.
-hipError_t launch_pairs_jobs(int scheme, const RankView& rv, int64_t m, int n, int64_t J_begin,
-                             int64_t J_end, const PairOut& out, const int32_t* status,
-                             hipStream_t s);
+int persistent_grid();
 
-// Persistent launch over all units of a descriptor table.
-hipError_t launch_pairs_batch(const BatchDesc* descs_dev, int64_t count, int64_t total_units,
-                              const int64_t* unit_prefix_dev, int64_t* counter_dev, int grid,
-                              int max_lanes, const int32_t* status, hipStream_t s);
+// ---- host helpers shared by the API units (ktau_api.hip)
 
-int persistent_grid(int max_lanes);
+struct WsLayout {
+  size_t perm, rank, rstart, n1, heavy, total;
+  int64_t ld;
+};
+WsLayout ws_layout(int64_t m, int64_t n);
+int check_shape(int64_t m, int64_t n);
+int env_int(const char* name, int dflt);
+// Descriptor of a matrix whose rank pre-pass lives in `ws`; status NULL means
+// the status word at the start of ws.
+MatDesc matdesc(void* ws, int64_t m, int64_t n, const ktau_pair_out& out, int scheme, int q,
+                int64_t J_begin, int64_t J_end, int32_t* status);
+int prepass_ws(const float* X, int64_t m, int64_t n, void* ws, int64_t* n1_out, int32_t* status,
+               hipStream_t s);
+// Zeroes `count` int32 words with a kernel (never a memset node in a graph).
+int clear_words(int32_t* p, int count, hipStream_t s);
 
 }  // namespace ktau

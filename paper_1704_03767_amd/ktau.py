@@ -57,6 +57,8 @@ def _declare(lib):
         "ktau_allpairs_range": ([p, i64, i64, i64, i64, _PairOut, p, sz, p], i32),
         "ktau_allpairs_ex": ([p, i64, i64, i64, i64, _PairOut, p, sz, i32, i32, p], i32),
         "ktau_status": ([p, p], i32),
+        "ktau_prepare": ([p, i64, i64, p, p, sz, p], i32),
+        "ktau_pairs": ([i64, i64, i64, i64, _PairOut, p, sz, i32, i32, p], i32),
         "ktau_scheme_count": ([], i32),
         "ktau_scheme_name": ([i32], ctypes.c_char_p),
         "ktau_scheme_capacity": ([i32], i64),
@@ -212,6 +214,24 @@ def ktau_allpairs_ex(X: torch.Tensor, J_begin: int, J_end: int, out: dict, works
     _check(lib().ktau_allpairs_ex(_ptr(X), m, n, J_begin, J_end, _pair_out(out), _ptr(workspace),
                                   workspace.numel(), scheme_id(scheme), int(q), _stream(stream)),
            "ktau_allpairs_ex")
+
+
+def ktau_prepare(X: torch.Tensor, workspace: torch.Tensor, n1_out: torch.Tensor | None = None,
+                 stream=None) -> None:
+    """Rank pre-pass of X into the workspace (first half of ktau_allpairs)."""
+    X = _as_matrix(X)
+    m, n = X.shape
+    _check(lib().ktau_prepare(_ptr(X), m, n, _ptr(n1_out), _ptr(workspace), workspace.numel(),
+                              _stream(stream)), "ktau_prepare")
+
+
+def ktau_pairs(m: int, n: int, out: dict, workspace: torch.Tensor, J_begin: int = -1,
+               J_end: int = -1, scheme=None, q: int = 0, stream=None) -> None:
+    """Pair kernel over jobs [J_begin, J_end) (all if J_begin < 0) of a
+    workspace prepared by ktau_prepare (second half of ktau_allpairs)."""
+    _check(lib().ktau_pairs(m, n, J_begin, J_end, _pair_out(out), _ptr(workspace),
+                            workspace.numel(), scheme_id(scheme), int(q), _stream(stream)),
+           "ktau_pairs")
 
 
 def ktau_status(workspace: torch.Tensor, stream=None) -> int:
