@@ -105,6 +105,9 @@ def main() -> int:
     ap.add_argument("--q", type=int, default=0, help="tile edge (default 8)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the measurement, copy this many MiB device to device once "
+                         "(a plain copy kernel of known size to scale HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -204,6 +207,11 @@ def main() -> int:
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(X, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+    if args.copy_calibration_mib > 0:
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     return 0
 
 

@@ -67,6 +67,7 @@ struct RankView {
   const uint16_t* rank;     // [rows][ld] sample -> dense rank
   const uint16_t* rstart;   // [rows][ld] sorted position -> first position of its tie run
   const int64_t* n1;        // [rows]
+  const int32_t* tie_end;   // [rows] 1 + last sorted position inside a tie run (0: no ties)
   int64_t ld;               // row stride in elements
 };
 
@@ -131,7 +132,7 @@ struct MatDesc {
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* status, hipStream_t s);
+                          int32_t* tie_end, int32_t* status, hipStream_t s);
 
 // Main pair kernel over all tiles (tiles = true) or over jobs
 // [J_begin, J_end), then the heavy-row pass and the composite pass.
@@ -148,7 +149,7 @@ int persistent_grid();
 // ---- host helpers shared by the API units (ktau_api.hip)
 
 struct WsLayout {
-  size_t perm, rank, rstart, n1, heavy, total;
+  size_t perm, rank, rstart, n1, tie_end, heavy, total;
   int64_t ld;
 };
 WsLayout ws_layout(int64_t m, int64_t n);

@@ -167,36 +167,40 @@ __device__ __forceinline__ bool pair_fast(const RankView& rv, int64_t y, int64_t
   uint32_t key[K];
 #pragma unroll
   for (int r = 0; r < K; ++r) key[r] = (k0 + r < n) ? (uint32_t)row[p[r]] : 0x7FFFu;
-  if (n1u == 0) {
-    nd = group_sum<G>(Net::count(key, lane, xbuf), red);
-    n3 = 0;
-    return true;
-  }
-  // v' in u order replaces the rank row once every lane has gathered
-  group_sync<G>();
-  {
-    uint16_t kv[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) kv[r] = (uint16_t)key[r];
-    if (in_row) store_u16<K>(row + k0, kv);
-  }
-  group_sync<G>();
-  // positions spread over lanes with stride G so that one tie run is shared
-  // by many lanes; each is compared with the earlier positions of its run
-  const uint16_t* ru = rv.rstart + u * rv.ld;
   uint32_t xin = 0, tie = 0;
-  for (int k = lane; k < n; k += G) {
-    const int s = ru[k];
-    const uint32_t me = row[k];
-    for (int j = s; j < k; ++j) {
-      const uint32_t o = row[j];
-      xin += o > me ? 1u : 0u;
-      tie += o == me ? 1u : 0u;
+  if (n1u != 0) {
+    // v' in u order replaces the rank row once every lane has gathered
+    group_sync<G>();
+    {
+      uint16_t kv[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) kv[r] = (uint16_t)key[r];
+      if (in_row) store_u16<K>(row + k0, kv);
+    }
+    group_sync<G>();
+    // positions up to the end of u's last tie run, spread over lanes with
+    // stride G so that one run is shared by many lanes; each is compared
+    // with the earlier positions of its run
+    const uint16_t* ru = rv.rstart + u * rv.ld;
+    const int end = rv.tie_end[u];
+    for (int k = lane; k < end; k += G) {
+      const int s = ru[k];
+      const uint32_t me = row[k];
+      for (int j = s; j < k; ++j) {
+        const uint32_t o = row[j];
+        xin += o > me ? 1u : 0u;
+        tie += o == me ? 1u : 0u;
+      }
     }
   }
   const uint32_t inv = group_sum<G>(Net::count(key, lane, xbuf), red);
-  nd = inv - group_sum<G>(xin, red);
-  n3 = group_sum<G>(tie, red);
+  if (n1u != 0) {
+    nd = inv - group_sum<G>(xin, red);
+    n3 = group_sum<G>(tie, red);
+  } else {
+    nd = inv;
+    n3 = 0;
+  }
   return true;
 }
 

@@ -71,10 +71,12 @@ __global__ void __launch_bounds__(kThreads)
 prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
                uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
-               int64_t* __restrict__ n1_out, int32_t* __restrict__ status) {
+               int64_t* __restrict__ n1_out, int32_t* __restrict__ tie_end,
+               int32_t* __restrict__ status) {
   extern __shared__ uint64_t s_keys[];
   __shared__ int s_scan[kThreads / 64];
   __shared__ unsigned long long s_n1;
+  __shared__ int s_tie_end;
   const int64_t row = blockIdx.x;
   if (row >= m) return;
   const float* x = X + row * (int64_t)n;
@@ -91,7 +93,10 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
     }
     s_keys[i] = w;
   }
-  if (tid == 0) s_n1 = 0;
+  if (tid == 0) {
+    s_n1 = 0;
+    s_tie_end = 0;
+  }
   if (__syncthreads_or(any_nan)) {
     if (tid == 0) atomicExch(status, KTAU_ENAN);
     return;
@@ -136,6 +141,7 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
   uint16_t* srow = rstart ? rstart + row * ld : nullptr;
   int r = rank_base, st = start_base;
   unsigned long long ties = 0;
+  int last_tied = 0;
   for (int c = 0; c < chunk; ++c) {
     int k = k0 + c;
     if (k < n) {
@@ -149,6 +155,7 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
       if (rrow) rrow[sample] = (uint16_t)r;
       if (srow) srow[k] = (uint16_t)st;
       ties += (unsigned long long)(k - st);
+      if (k > st) last_tied = k + 1;
     } else if (k < ld) {
       if (prow) prow[k] = 0;
       if (srow) srow[k] = (uint16_t)k;
@@ -163,10 +170,12 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
   if (rrow)
     for (int i = n + tid; i < ld; i += kThreads) rrow[i] = 0;
   atomicAdd(&s_n1, ties);
+  atomicMax(&s_tie_end, last_tied);
   __syncthreads();
   if (tid == 0) {
     if (n1_ws) n1_ws[row] = (int64_t)s_n1;
     if (n1_out) n1_out[row] = (int64_t)s_n1;
+    if (tie_end) tie_end[row] = s_tie_end;
   }
 }
 
@@ -174,12 +183,12 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* status, hipStream_t s) {
+                          int32_t* tie_end, int32_t* status, hipStream_t s) {
   int npow2 = 64;
   while (npow2 < n) npow2 <<= 1;
   size_t lds = (size_t)npow2 * sizeof(uint64_t);
   hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)m), dim3(kThreads), lds, s, X, m, (int)n,
-                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, status);
+                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, tie_end, status);
   return hipGetLastError();
 }
 
