@@ -164,6 +164,63 @@ int ktau_default_scheme(int64_t n);
 int ktau_allpairs_ex(const float* X_dev, int64_t m, int64_t n, int64_t J_begin,
                      int64_t J_end, ktau_pair_out out, void* workspace_dev,
                      size_t ws_bytes, int scheme, int q, void* stream);
+/* ---------------------------------------------------------------------------
+ * Batched all-pairs: many independent matrices of uneven (m, n) in one
+ * persistent launch.  Workgroups take q x q tiles (Sec. 4.2) of any matrix
+ * from one atomic counter -- the shared-counter distribution that Sec. 4.1
+ * names for jobs of varied cost -- so small matrices do not leave the device
+ * idle.  The launch sequence (status clear, one pre-pass over all rows, the
+ * persistent pair kernel, the heavy-tie composite pass) is captured in a
+ * hipGraph on the first ktau_batch_run and replayed afterwards.
+ * ------------------------------------------------------------------------- */
+
+typedef struct ktau_matrix {
+  const float* X_dev;   /* m x n float32, row-major; read by every run        */
+  int64_t m, n;         /* 2 <= m, 2 <= n <= KTAU_MAX_N                        */
+  ktau_pair_out out;    /* device results for all m(m-1)/2 strict jobs; NULLs ok */
+} ktau_matrix;
+
+typedef struct ktau_batch_opts {
+  int32_t use_graph;      /* 1 (default): capture once in a hipGraph, replay   */
+  int32_t autotune;       /* 1 (default): (scheme, q) per sample-count class by
+                             measurement on this device; 0: built-in defaults   */
+  int32_t force_scheme;   /* >= 0: this scheme for every matrix (-1 default)   */
+  int32_t force_q;        /* > 0: this tile edge for every matrix (0 default)  */
+  const char* tune_cache; /* autotune cache file (NULL: $KTAU_TUNE_CACHE, else
+                             in-process only)                                   */
+} ktau_batch_opts;
+
+typedef struct ktau_batch ktau_batch;   /* opaque plan, owned by the library */
+
+void ktau_batch_default_opts(ktau_batch_opts* opts_host);
+
+/* Validates every matrix, chooses each one's (scheme, q), and allocates the
+ * plan's device arena (rank workspaces for all matrices plus descriptors;
+ * about 6 m ceil64(n) bytes per matrix).  The matrices' X_dev and output
+ * arrays are the caller's and must stay valid while the plan is used.
+ * Autotuning, when a sample-count class is not yet tuned, runs timing
+ * launches on `stream` and blocks until they finish. */
+int ktau_batch_create(const ktau_matrix* mats_host, int64_t count,
+                      const ktau_batch_opts* opts_host, void* stream,
+                      ktau_batch** plan_out);
+
+/* Enqueues one full run of the plan on `stream` (asynchronous). */
+int ktau_batch_run(ktau_batch* plan, void* stream);
+
+/* Waits for `stream`; KTAU_ENAN if any matrix of the last run held a NaN. */
+int ktau_batch_status(ktau_batch* plan, void* stream);
+
+/* The (scheme, q) chosen for matrix i. */
+int ktau_batch_plan(const ktau_batch* plan, int64_t i, int32_t* scheme_host,
+                    int32_t* q_host);
+
+void ktau_batch_destroy(ktau_batch* plan);
+
+/* Autotuner: for each n in ns_host, the (scheme, q) the batch planner would
+ * use, tuning any class not yet in the process table or the cache file
+ * (timing launches on `stream`, synchronous). */
+int ktau_autotune(const int64_t* ns_host, int64_t count, const char* cache_path,
+                  void* stream, int32_t* schemes_out_host, int32_t* q_out_host);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,457 @@
+// Batched all-pairs over many independent matrices of uneven (m, n), and the
+// autotuner that picks the per-pair scheme and tile edge for each sample-count
+// class.
+//
+// A batch plan owns one device arena: a shared status word, one rank
+// workspace per matrix (the plain layout), the descriptor table and the unit
+// (tile) and row prefixes.  One run is: clear status and tile counters; one
+// pre-pass launch over every row of every matrix; for each scheme class
+// present, one persistent pair launch whose workgroups take tiles of any
+// matrix of the class from an atomic counter (Sec. 4.1 notes a shared counter
+// balances jobs of varied cost) -- the classes run as parallel branches, each
+// kernel with its own register budget; then the heavy-row and composite
+// passes.  The sequence is captured once in a hipGraph and replayed.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ktau_internal.h"
+
+namespace ktau {
+namespace {
+
+// ------------------------------------------------------------- autotuner
+
+// Sample-count class of n: the smallest scheme capacity that holds it.
+int64_t n_class(int64_t n) {
+  int64_t c = 128;
+  while (c < n) c <<= 1;
+  return c;
+}
+
+struct Plan {
+  int scheme;
+  int q;
+  double pairs_per_s;
+};
+
+std::mutex g_tune_mu;
+std::map<int64_t, Plan> g_tuned;   // n class -> best plan (process-wide)
+
+// Cache file: one line per class, "n_class scheme_name q pairs_per_s".
+void load_cache(const char* path) {
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char name[64];
+  long long cls;
+  int q;
+  double pps;
+  while (fscanf(f, "%lld %63s %d %lf", &cls, name, &q, &pps) == 4) {
+    for (int s = 0; s < kNumSchemes; ++s)
+      if (strcmp(name, scheme_name(s)) == 0 && scheme_capacity(s) >= cls && q >= 1 && q <= 64)
+        g_tuned[cls] = Plan{s, q, pps};
+  }
+  fclose(f);
+}
+
+void save_cache(const char* path) {
+  if (!path || !*path) return;
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (auto& kv : g_tuned)
+    fprintf(f, "%lld %s %d %.6e\n", (long long)kv.first, scheme_name(kv.second.scheme),
+            kv.second.q, kv.second.pairs_per_s);
+  fclose(f);
+  rename(tmp.c_str(), path);
+}
+
+// Deterministic tie-free test matrix for timing (splitmix64 of the index).
+__global__ void synth_kernel(float* X, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  X[i] = (float)(z >> 40) * (1.0f / 16777216.0f);
+}
+
+// Candidate schemes for a class: those that hold the class without more
+// than doubling the padding.
+std::vector<int> candidates(int64_t cls) {
+  std::vector<int> v;
+  for (int s = 0; s < kNumSchemes; ++s)
+    if (scheme_capacity(s) >= cls && scheme_capacity(s) < 2 * cls) v.push_back(s);
+  return v;
+}
+
+// Measures every (scheme, q) candidate of class `cls` on a synthetic matrix
+// of m_t x cls and records the fastest.
+int tune_class(int64_t cls, hipStream_t s) {
+  const int64_t n = cls, m = 768;
+  const WsLayout L = ws_layout(m, n);
+  float* X = nullptr;
+  void* ws = nullptr;
+  double* tau = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = KTAU_OK;
+  const int64_t P = m * (m - 1) / 2;
+  if (hipMalloc(&X, (size_t)(m * n) * sizeof(float)) != hipSuccess ||
+      hipMalloc(&ws, L.total) != hipSuccess || hipMalloc(&tau, (size_t)P * sizeof(double)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = KTAU_ENOMEM;
+  }
+  Plan best{default_scheme(n), 8, 0.0};
+  if (rc == KTAU_OK) {
+    hipLaunchKernelGGL(synth_kernel, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, X,
+                       m * n);
+    if (hipGetLastError() != hipSuccess || clear_words((int32_t*)ws, 2, s) != KTAU_OK ||
+        prepass_ws(X, m, n, ws, nullptr, nullptr, s) != KTAU_OK)
+      rc = KTAU_EDEVICE;
+  }
+  if (rc == KTAU_OK) {
+    ktau_pair_out out{};
+    out.tau_b = tau;
+    for (int scheme : candidates(cls)) {
+      for (int q : {4, 8, 16}) {
+        MatDesc d = matdesc(ws, m, n, out, scheme, q, 0, P, nullptr);
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+          if (hipEventRecord(e0, s) != hipSuccess || launch_pairs_plain(d, true, s) != hipSuccess ||
+              hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = KTAU_EDEVICE;
+            break;
+          }
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
+          if (rep > 0) best_ms = std::min(best_ms, ms);
+        }
+        if (rc != KTAU_OK) break;
+        const double pps = (double)P / (best_ms * 1e-3);
+        if (pps > best.pairs_per_s) best = Plan{scheme, q, pps};
+      }
+      if (rc != KTAU_OK) break;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (X) (void)hipFree(X);
+  if (ws) (void)hipFree(ws);
+  if (tau) (void)hipFree(tau);
+  if (rc == KTAU_OK) g_tuned[cls] = best;
+  return rc;
+}
+
+Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* rc) {
+  const int64_t cls = n_class(n);
+  if (!autotune) return Plan{default_scheme(n), env_int("KTAU_TILE_Q", 8), 0.0};
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tuned.find(cls);
+  if (it == g_tuned.end()) {
+    load_cache(cache);
+    it = g_tuned.find(cls);
+  }
+  if (it == g_tuned.end()) {
+    *rc = tune_class(cls, s);
+    if (*rc != KTAU_OK) return Plan{default_scheme(n), 8, 0.0};
+    save_cache(cache);
+    it = g_tuned.find(cls);
+  }
+  Plan p = it->second;
+  if (scheme_capacity(p.scheme) < n) p.scheme = default_scheme(n);
+  return p;
+}
+
+}  // namespace
+}  // namespace ktau
+
+using namespace ktau;
+
+// One scheme class of a batch: a contiguous slice of the descriptor table,
+// launched as its own persistent kernel on its own branch of the graph.
+struct ClassRun {
+  int scheme;
+  int64_t first, count;          // slice of the descriptor table
+  int64_t total_units;
+  int64_t* prefix = nullptr;     // device [count + 1], unit prefix inside the class
+  int64_t* counter = nullptr;    // device tile counter
+  hipStream_t stream = nullptr;  // branch stream (default priority)
+  hipEvent_t done = nullptr;
+};
+
+struct ktau_batch {
+  int64_t count = 0;
+  std::vector<MatDesc> host_descs;   // class-sorted
+  std::vector<int64_t> slot;         // caller index -> descriptor position
+  std::vector<ClassRun> classes;
+  char* arena = nullptr;             // device memory owned by the plan
+  MatDesc* descs = nullptr;          // device, class-sorted
+  int64_t* row_prefix = nullptr;     // device [count + 1]
+  int32_t* words = nullptr;          // device: [0] status; int64 counters from byte 64
+  int64_t total_rows = 0;
+  int max_n = 0;
+  bool use_graph = true;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+constexpr int kClearWords = 32;      // status word + up to 7 int64 counters
+
+// The whole run on stream s: the scheme classes fork onto their own streams
+// after the pre-pass and join before the tie passes.
+int enqueue_batch(ktau_batch* b, hipStream_t s) {
+  if (clear_words(b->words, kClearWords, s) != KTAU_OK) return KTAU_EDEVICE;
+  if (launch_prepass_batch(b->descs, b->count, b->total_rows, b->row_prefix, b->max_n, s) !=
+      hipSuccess)
+    return KTAU_EDEVICE;
+  if (hipEventRecord(b->fork, s) != hipSuccess) return KTAU_EDEVICE;
+  for (ClassRun& c : b->classes) {
+    if (hipStreamWaitEvent(c.stream, b->fork, 0) != hipSuccess) return KTAU_EDEVICE;
+    if (launch_pairs_persistent(c.scheme, b->descs + c.first, c.count, c.total_units, c.prefix,
+                                c.counter, b->words, c.stream) != hipSuccess)
+      return KTAU_EDEVICE;
+    if (hipEventRecord(c.done, c.stream) != hipSuccess) return KTAU_EDEVICE;
+  }
+  for (ClassRun& c : b->classes)
+    if (hipStreamWaitEvent(s, c.done, 0) != hipSuccess) return KTAU_EDEVICE;
+  if (launch_tie_passes_batch(b->descs, b->count, s) != hipSuccess) return KTAU_EDEVICE;
+  return KTAU_OK;
+}
+
+void free_batch(ktau_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (ClassRun& c : b->classes) {
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    if (c.done) (void)hipEventDestroy(c.done);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->arena) (void)hipFree(b->arena);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ktau_batch_default_opts(ktau_batch_opts* o) {
+  if (!o) return;
+  o->use_graph = 1;
+  o->autotune = 1;
+  o->force_scheme = -1;
+  o->force_q = 0;
+  o->tune_cache = nullptr;
+}
+
+int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_opts* opts,
+                      void* stream, ktau_batch** out) {
+  if (!mats || count < 1 || !out) return KTAU_EINVAL;
+  *out = nullptr;
+  ktau_batch_opts o;
+  ktau_batch_default_opts(&o);
+  if (opts) o = *opts;
+  for (int64_t i = 0; i < count; ++i) {
+    const int rc = check_shape(mats[i].m, mats[i].n);
+    if (rc != KTAU_OK) return rc;
+    if (!mats[i].X_dev) return KTAU_EINVAL;
+  }
+  if (o.force_scheme >= kNumSchemes || o.force_q < 0 || o.force_q > 64) return KTAU_EINVAL;
+  if (o.force_scheme >= 0)
+    for (int64_t i = 0; i < count; ++i)
+      if (scheme_capacity(o.force_scheme) < mats[i].n) return KTAU_EINVAL;
+  const hipStream_t s = (hipStream_t)stream;
+  const char* cache = o.tune_cache ? o.tune_cache : getenv("KTAU_TUNE_CACHE");
+
+  // plans, then the class-sorted order
+  std::vector<Plan> plans(count);
+  for (int64_t i = 0; i < count; ++i) {
+    int rc = KTAU_OK;
+    plans[i] = plan_for(mats[i].n, o.autotune != 0 && o.force_scheme < 0, cache, s, &rc);
+    if (rc != KTAU_OK) return rc;
+    if (o.force_scheme >= 0) plans[i].scheme = o.force_scheme;
+    if (o.force_q > 0) plans[i].q = o.force_q;
+  }
+  std::vector<int64_t> order(count);
+  for (int64_t i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t c) { return plans[a].scheme < plans[c].scheme; });
+
+  ktau_batch* b = new ktau_batch();
+  b->count = count;
+  b->use_graph = o.use_graph != 0;
+  b->slot.resize(count);
+  for (int64_t p = 0; p < count; ++p) b->slot[order[p]] = p;
+  for (int64_t p = 0; p < count; ++p) {
+    const int sc = plans[order[p]].scheme;
+    if (b->classes.empty() || b->classes.back().scheme != sc) {
+      ClassRun c;
+      c.scheme = sc;
+      c.first = p;
+      c.count = 0;
+      c.total_units = 0;
+      b->classes.push_back(c);
+    }
+    b->classes.back().count++;
+  }
+  const int64_t ncls = (int64_t)b->classes.size();
+  // arena: words | descs | row prefix | class unit prefixes | workspaces
+  size_t off = 256;
+  const size_t desc_off = off;
+  off = (size_t)round_up((int64_t)(off + (size_t)count * sizeof(MatDesc)), (int64_t)kAlign);
+  const size_t rp_off = off;
+  off = (size_t)round_up((int64_t)(off + (size_t)(count + 1) * 8), (int64_t)kAlign);
+  const size_t up_off = off;
+  off = (size_t)round_up((int64_t)(off + (size_t)(count + ncls) * 8), (int64_t)kAlign);
+  std::vector<size_t> ws_off(count);
+  for (int64_t p = 0; p < count; ++p) {
+    const ktau_matrix& mt = mats[order[p]];
+    ws_off[p] = off;
+    off += ws_layout(mt.m, mt.n).total;
+  }
+  if (hipMalloc((void**)&b->arena, off) != hipSuccess) {
+    delete b;
+    return KTAU_ENOMEM;
+  }
+  b->words = (int32_t*)b->arena;
+  b->descs = (MatDesc*)(b->arena + desc_off);
+  b->row_prefix = (int64_t*)(b->arena + rp_off);
+  int64_t* up_dev = (int64_t*)(b->arena + up_off);
+
+  std::vector<int64_t> rprefix(count + 1, 0), uprefix;
+  b->host_descs.resize(count);
+  for (int64_t c = 0; c < ncls; ++c) {
+    ClassRun& cr = b->classes[c];
+    cr.prefix = up_dev + cr.first + c;
+    cr.counter = (int64_t*)(b->arena + 64) + c;
+    int64_t acc = 0;
+    uprefix.push_back(0);
+    for (int64_t p = cr.first; p < cr.first + cr.count; ++p) {
+      const ktau_matrix& mt = mats[order[p]];
+      const Plan& pl = plans[order[p]];
+      MatDesc d = matdesc(b->arena + ws_off[p], mt.m, mt.n, mt.out, pl.scheme, pl.q, 0,
+                          mt.m * (mt.m - 1) / 2, b->words);
+      d.X = mt.X_dev;
+      d.n1_out = mt.out.n1;
+      d.unit_begin = acc;
+      acc += d.n_units;
+      uprefix.push_back(acc);
+      rprefix[p + 1] = rprefix[p] + mt.m;
+      b->host_descs[p] = d;
+      b->max_n = std::max(b->max_n, (int)mt.n);
+    }
+    cr.total_units = acc;
+  }
+  b->total_rows = rprefix[count];
+  int rc = KTAU_OK;
+  if (hipMemcpy(b->descs, b->host_descs.data(), (size_t)count * sizeof(MatDesc),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->row_prefix, rprefix.data(), (size_t)(count + 1) * 8,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(up_dev, uprefix.data(), uprefix.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    rc = KTAU_EDEVICE;
+  if (rc == KTAU_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+    rc = KTAU_EDEVICE;
+  for (ClassRun& c : b->classes) {
+    if (rc != KTAU_OK) break;
+    if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess)
+      rc = KTAU_EDEVICE;
+  }
+  // query each class kernel's occupancy now, outside any capture
+  for (ClassRun& c : b->classes) {
+    if (rc != KTAU_OK) break;
+    if (launch_pairs_persistent(c.scheme, b->descs, 0, 0, nullptr, nullptr, b->words, s) !=
+        hipSuccess)
+      rc = KTAU_EDEVICE;
+  }
+  if (rc != KTAU_OK) {
+    free_batch(b);
+    return rc;
+  }
+  *out = b;
+  return KTAU_OK;
+}
+
+int ktau_batch_run(ktau_batch* b, void* stream) {
+  if (!b) return KTAU_EINVAL;
+  const hipStream_t s = (hipStream_t)stream;
+  if (!b->use_graph) return enqueue_batch(b, s);
+  // first run: capture the whole sequence (with its fork/join branches) once
+  if (!b->exec) {
+    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return KTAU_EDEVICE;
+    if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return KTAU_EDEVICE;
+    const int rc = enqueue_batch(b, b->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc != KTAU_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != KTAU_OK ? rc : KTAU_EDEVICE;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      b->exec = nullptr;
+      return KTAU_EDEVICE;
+    }
+  }
+  return hipGraphLaunch(b->exec, s) == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
+}
+
+int ktau_batch_status(ktau_batch* b, void* stream) {
+  if (!b) return KTAU_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return KTAU_EDEVICE;
+  int32_t st = 0;
+  if (hipMemcpy(&st, b->words, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return KTAU_EDEVICE;
+  return st;
+}
+
+int ktau_batch_plan(const ktau_batch* b, int64_t i, int32_t* scheme, int32_t* q) {
+  if (!b || i < 0 || i >= b->count) return KTAU_EINVAL;
+  const MatDesc& d = b->host_descs[b->slot[i]];
+  if (scheme) *scheme = d.scheme;
+  if (q) *q = d.q;
+  return KTAU_OK;
+}
+
+void ktau_batch_destroy(ktau_batch* b) {
+  if (b) free_batch(b);
+}
+
+int ktau_autotune(const int64_t* ns, int64_t count, const char* cache_path, void* stream,
+                  int32_t* schemes_out, int32_t* q_out) {
+  if (!ns || count < 0) return KTAU_EINVAL;
+  for (int64_t i = 0; i < count; ++i) {
+    if (ns[i] < 2) return KTAU_EINVAL;
+    if (ns[i] > KTAU_MAX_N) return KTAU_ERANGE;
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    int rc = KTAU_OK;
+    const Plan p = plan_for(ns[i], true, cache_path, (hipStream_t)stream, &rc);
+    if (rc != KTAU_OK) return rc;
+    if (schemes_out) schemes_out[i] = p.scheme;
+    if (q_out) q_out[i] = p.q;
+  }
+  if (cache_path && *cache_path) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    save_cache(cache_path);
+  }
+  return KTAU_OK;
+}
+
+}  // extern "C"

@@ -114,6 +114,8 @@ __host__ __device__ inline int64_t direct_budget(int64_t n) {
 struct MatDesc {
   RankView rv;
   PairOut out;
+  const float* X;         // input rows (batched pre-pass)
+  int64_t* n1_out;        // optional copy of n1 for the caller
   const int32_t* status;  // device status word (non-zero: skip all work)
   int32_t* heavy;         // [m] list of heavy rows (written by the heavy pass)
   int32_t* heavy_count;   // device scalar
@@ -134,17 +136,22 @@ hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, 
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
                           int32_t* tie_end, int32_t* status, hipStream_t s);
 
+// Rank pre-pass of every row of every matrix of a descriptor table.
+hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t total_rows,
+                                const int64_t* row_prefix_dev, int max_n, hipStream_t s);
+
 // Main pair kernel over all tiles (tiles = true) or over jobs
 // [J_begin, J_end), then the heavy-row pass and the composite pass.
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s);
 
-// Persistent launch over all units of a descriptor table, then the heavy-row
-// and composite passes of every matrix.
-hipError_t launch_pairs_batch(const MatDesc* descs_dev, int64_t count, int64_t total_units,
-                              const int64_t* unit_prefix_dev, int64_t* counter_dev, int grid,
-                              const int32_t* status, hipStream_t s);
+// Persistent launch of one scheme over the tiles of the matrices of a
+// descriptor table (all of that scheme), taking tiles from *counter_dev.
+hipError_t launch_pairs_persistent(int scheme, const MatDesc* descs_dev, int64_t count,
+                                   int64_t total_units, const int64_t* unit_prefix_dev,
+                                   int64_t* counter_dev, const int32_t* status, hipStream_t s);
 
-int persistent_grid();
+// Heavy-row lists and the composite pass for every matrix of a table.
+hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, hipStream_t s);
 
 // ---- host helpers shared by the API units (ktau_api.hip)
 

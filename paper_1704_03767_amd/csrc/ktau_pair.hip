@@ -257,18 +257,16 @@ __global__ void __launch_bounds__(kBlock) pairs_jobs_kernel(MatDesc d) {
   }
 }
 
-// Persistent launch over the concatenated tile spaces of many matrices.
-// Units (tiles) are taken from an atomic counter; a unit is located by binary
-// search on the per-matrix unit prefix, then Eq. 13-14 inside its matrix.
-constexpr int kBatchLdsWords = FastLds<16, 256>::kWords > 4 * FastLds<16, 64>::kWords
-                                   ? FastLds<16, 256>::kWords
-                                   : 4 * FastLds<16, 64>::kWords;
-
+// Persistent launch over the concatenated tile spaces of the matrices of one
+// scheme class.  Units (tiles) are taken from an atomic counter; a unit is
+// located by binary search on the per-matrix unit prefix, then Eq. 13-14
+// inside its matrix.
+template <int K, int G>
 __global__ void __launch_bounds__(kBlock)
-pairs_batch_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_t total_units,
-                   const int64_t* __restrict__ unit_prefix, int64_t* __restrict__ counter,
-                   const int32_t* __restrict__ status) {
-  __shared__ uint32_t lds[kBatchLdsWords];
+pairs_persistent_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_t total_units,
+                        const int64_t* __restrict__ unit_prefix, int64_t* __restrict__ counter,
+                        const int32_t* __restrict__ status) {
+  __shared__ uint32_t lds[(kBlock / G) * FastLds<K, G>::kWords];
   __shared__ uint32_t red[kWavesPerBlock];
   __shared__ int64_t s_unit;
   if (*status != 0) return;
@@ -285,17 +283,7 @@ pairs_batch_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_t tot
       if (unit_prefix[mid] <= unit) lo = mid;
       else hi = mid - 1;
     }
-    const MatDesc d = descs[lo];
-    const int64_t t = unit - d.unit_begin;
-    switch (d.scheme) {
-      case kWaveK2: tile_pairs<2, 64>(d, t, lds, red); break;
-      case kWaveK4: tile_pairs<4, 64>(d, t, lds, red); break;
-      case kWaveK8: tile_pairs<8, 64>(d, t, lds, red); break;
-      case kWaveK16: tile_pairs<16, 64>(d, t, lds, red); break;
-      case kBlockK4: tile_pairs<4, 256>(d, t, lds, red); break;
-      case kBlockK8: tile_pairs<8, 256>(d, t, lds, red); break;
-      default: tile_pairs<16, 256>(d, t, lds, red); break;
-    }
+    tile_pairs<K, G>(descs[lo], unit - unit_prefix[lo], lds, red);
   }
 }
 
@@ -545,11 +533,14 @@ __global__ void __launch_bounds__(kBlock) composite_batch_kernel(const MatDesc* 
 }
 
 int device_cus() {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
-  }
+  static const int cus = [] {
+    int dev = 0, v = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t p;
+      if (hipGetDeviceProperties(&p, dev) == hipSuccess) v = p.multiProcessorCount;
+    }
+    return v;
+  }();
   return cus;
 }
 
@@ -612,24 +603,43 @@ hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
-int persistent_grid() {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pairs_batch_kernel, kBlock, 0) !=
-          hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  return device_cus() * per_cu;
+template <int K, int G>
+hipError_t persistent_t(const MatDesc* descs, int64_t count, int64_t total_units,
+                        const int64_t* prefix, int64_t* counter, const int32_t* status,
+                        hipStream_t s) {
+  // occupancy is queried once per scheme (first call, outside any capture)
+  static const int per_cu = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, pairs_persistent_kernel<K, G>, kBlock,
+                                                     0) != hipSuccess ||
+        v < 1)
+      v = 1;
+    return v;
+  }();
+  int64_t grid = (int64_t)device_cus() * per_cu;
+  if (grid > total_units) grid = total_units;
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL((pairs_persistent_kernel<K, G>), dim3((unsigned)grid), dim3(kBlock), 0, s,
+                     descs, count, total_units, prefix, counter, status);
+  return hipGetLastError();
 }
 
-hipError_t launch_pairs_batch(const MatDesc* descs_dev, int64_t count, int64_t total_units,
-                              const int64_t* unit_prefix_dev, int64_t* counter_dev, int grid,
-                              const int32_t* status, hipStream_t s) {
-  if (total_units > 0) {
-    hipLaunchKernelGGL(pairs_batch_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, descs_dev,
-                       count, total_units, unit_prefix_dev, counter_dev, status);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_pairs_persistent(int scheme, const MatDesc* d, int64_t count, int64_t total,
+                                   const int64_t* prefix, int64_t* counter, const int32_t* status,
+                                   hipStream_t s) {
+  switch (scheme) {
+    case kWaveK2: return persistent_t<2, 64>(d, count, total, prefix, counter, status, s);
+    case kWaveK4: return persistent_t<4, 64>(d, count, total, prefix, counter, status, s);
+    case kWaveK8: return persistent_t<8, 64>(d, count, total, prefix, counter, status, s);
+    case kWaveK16: return persistent_t<16, 64>(d, count, total, prefix, counter, status, s);
+    case kBlockK4: return persistent_t<4, 256>(d, count, total, prefix, counter, status, s);
+    case kBlockK8: return persistent_t<8, 256>(d, count, total, prefix, counter, status, s);
+    case kBlockK16: return persistent_t<16, 256>(d, count, total, prefix, counter, status, s);
+    default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(heavy_batch_kernel, dim3((unsigned)count), dim3(kBlock), 0, s, descs_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

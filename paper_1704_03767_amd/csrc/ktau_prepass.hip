@@ -67,18 +67,16 @@ __device__ inline int block_excl_max(int v, int* sh) {
   return max(base, excl_in_wave);
 }
 
-__global__ void __launch_bounds__(kThreads)
-prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
-               uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
-               uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
-               int64_t* __restrict__ n1_out, int32_t* __restrict__ tie_end,
-               int32_t* __restrict__ status) {
-  extern __shared__ uint64_t s_keys[];
+// Ranks row `row` of one matrix; s_keys holds npow2 64-bit words.
+__device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int npow2,
+                            uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
+                            uint16_t* __restrict__ rstart, int64_t ld,
+                            int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
+                            int32_t* __restrict__ tie_end, int32_t* __restrict__ status,
+                            uint64_t* s_keys) {
   __shared__ int s_scan[kThreads / 64];
   __shared__ unsigned long long s_n1;
   __shared__ int s_tie_end;
-  const int64_t row = blockIdx.x;
-  if (row >= m) return;
   const float* x = X + row * (int64_t)n;
   const int tid = threadIdx.x;
 
@@ -179,7 +177,51 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
   }
 }
 
+__global__ void __launch_bounds__(kThreads)
+prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
+               uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
+               uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
+               int64_t* __restrict__ n1_out, int32_t* __restrict__ tie_end,
+               int32_t* __restrict__ status) {
+  extern __shared__ uint64_t s_keys[];
+  const int64_t row = blockIdx.x;
+  if (row >= m) return;
+  prepass_row(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, tie_end, status, s_keys);
+}
+
+// Every row of every matrix of a batch: block b ranks global row b, found by
+// binary search on the per-matrix row prefix.
+__global__ void __launch_bounds__(kThreads)
+prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
+                     const int64_t* __restrict__ row_prefix) {
+  extern __shared__ uint64_t s_keys[];
+  const int64_t g = blockIdx.x;
+  int64_t lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (row_prefix[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const MatDesc& d = descs[lo];
+  const int64_t row = g - row_prefix[lo];
+  int npow2 = 64;
+  while (npow2 < d.n) npow2 <<= 1;
+  prepass_row(d.X, row, d.n, npow2, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
+              (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
+              (int32_t*)d.rv.tie_end, (int32_t*)d.status, s_keys);
+}
+
 }  // namespace
+
+hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t total_rows,
+                                const int64_t* row_prefix_dev, int max_n, hipStream_t s) {
+  int npow2 = 64;
+  while (npow2 < max_n) npow2 <<= 1;
+  const size_t lds = (size_t)npow2 * sizeof(uint64_t);
+  hipLaunchKernelGGL(prepass_batch_kernel, dim3((unsigned)total_rows), dim3(kThreads), lds, s,
+                     descs_dev, count, row_prefix_dev);
+  return hipGetLastError();
+}
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,

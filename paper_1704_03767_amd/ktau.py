@@ -287,3 +287,108 @@ def ktau_allpairs_range(X: torch.Tensor, J_begin: int, J_end: int, out: dict | N
         if st != KTAU_OK:
             raise KtauError(st, "ktau_allpairs_range")
     return out
+
+
+# ------------------------------------------------------------------ batched
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("X_dev", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("out", _PairOut)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("force_scheme", ctypes.c_int32), ("force_q", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+def _declare_batch(L):
+    i64, i32, p = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+    decl = {
+        "ktau_batch_default_opts": ([p], None),
+        "ktau_batch_create": ([p, i64, p, p, p], i32),
+        "ktau_batch_run": ([p, p], i32),
+        "ktau_batch_status": ([p, p], i32),
+        "ktau_batch_plan": ([p, i64, p, p], i32),
+        "ktau_batch_destroy": ([p], None),
+        "ktau_autotune": ([p, i64, ctypes.c_char_p, p, p, p], i32),
+    }
+    for name, (args, res) in decl.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+def _blib():
+    L = lib()
+    if not hasattr(L, "_ktau_batch_declared"):
+        _declare_batch(L)
+        L._ktau_batch_declared = True
+    return L
+
+
+class KtauBatch:
+    """A batch plan (ktau_batch_create) over CUDA float32 matrices.
+
+    ``outs[i]`` is a dict of result tensors like alloc_outputs() returns; if
+    omitted they are allocated.  The tensors are kept alive by the plan."""
+
+    def __init__(self, mats, outs=None, use_graph=True, autotune=True, force_scheme=None,
+                 force_q=0, tune_cache=None, stream=None):
+        L = _blib()
+        self._mats = [_as_matrix(X) for X in mats]
+        if outs is None:
+            outs = [alloc_outputs(X.shape[0] * (X.shape[0] - 1) // 2, X.shape[0], X.device)
+                    for X in self._mats]
+        self.outs = outs
+        arr = (_Matrix * len(self._mats))()
+        for i, (X, o) in enumerate(zip(self._mats, outs)):
+            arr[i] = _Matrix(ctypes.c_void_p(X.data_ptr()), X.shape[0], X.shape[1], _pair_out(o))
+        opts = _BatchOpts()
+        L.ktau_batch_default_opts(ctypes.byref(opts))
+        opts.use_graph = 1 if use_graph else 0
+        opts.autotune = 1 if autotune else 0
+        opts.force_scheme = -1 if force_scheme is None else scheme_id(force_scheme)
+        opts.force_q = int(force_q)
+        self._cache = tune_cache.encode() if tune_cache else None
+        opts.tune_cache = self._cache
+        h = ctypes.c_void_p()
+        _check(L.ktau_batch_create(arr, len(self._mats), ctypes.byref(opts), _stream(stream),
+                                   ctypes.byref(h)), "ktau_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_blib().ktau_batch_run(self._h, _stream(stream)), "ktau_batch_run")
+
+    def status(self, stream=None) -> int:
+        return int(_blib().ktau_batch_status(self._h, _stream(stream)))
+
+    def plan(self, i: int) -> tuple[str, int]:
+        s, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(_blib().ktau_batch_plan(self._h, i, ctypes.byref(s), ctypes.byref(q)),
+               "ktau_batch_plan")
+        return ktau_scheme_names()[s.value], q.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _blib().ktau_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ktau_autotune(ns, cache_path: str | None = None, stream=None) -> list[tuple[str, int]]:
+    L = _blib()
+    arr = (ctypes.c_int64 * len(ns))(*ns)
+    sch = (ctypes.c_int32 * len(ns))()
+    qs = (ctypes.c_int32 * len(ns))()
+    _check(L.ktau_autotune(arr, len(ns), cache_path.encode() if cache_path else None,
+                           _stream(stream), sch, qs), "ktau_autotune")
+    names = ktau_scheme_names()
+    return [(names[s], q) for s, q in zip(sch, qs)]
