@@ -96,6 +96,56 @@ def cpu_baseline(X, seconds: float, seed: int = 99) -> dict:
                       f"({platform.processor() or platform.machine()})"}
 
 
+def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
+    """256 matrices, m ~ U[32, 2048], n ~ U[64, 4096], N(0,1) with 20% of the
+    entries on a 0.25 grid (seed 4): 256 plain calls vs one batched plan."""
+    import numpy as np
+
+    mats = synth.batch(256, 4)
+    dev = [torch.from_numpy(X).cuda() for X in mats]
+    del mats
+    outs = [K.alloc_outputs(X.shape[0] * (X.shape[0] - 1) // 2, X.shape[0], X.device)
+            for X in dev]
+    pairs = sum(X.shape[0] * (X.shape[0] - 1) // 2 for X in dev)
+    steps = sum(X.shape[0] * (X.shape[0] - 1) // 2 * merge_steps(X.shape[1]) for X in dev)
+    ws = torch.empty(max(K.ktau_allpairs_workspace_size(*X.shape) for X in dev),
+                     dtype=torch.uint8, device="cuda")
+
+    def plain():
+        for X, o in zip(dev, outs):
+            K.ktau_prepare(X, ws, o["n1"], stream=stream)
+            K.ktau_pairs(X.shape[0], X.shape[1], o, ws, stream=stream)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_plain = timed(plain)
+    if K.ktau_status(ws) != K.KTAU_OK:
+        raise RuntimeError("uneven batch: plain calls failed")
+    plan = K.KtauBatch(dev, outs=outs, stream=stream)
+    ms_batch = timed(lambda: plan.run(stream))
+    if plan.status(stream) != K.KTAU_OK:
+        raise RuntimeError("uneven batch: batched run failed")
+    classes = sorted({plan.plan(i) for i in range(len(dev))})
+    plan.close()
+    return {"workload": "256 matrices m~U[32,2048] n~U[64,4096], 20% of entries on a 0.25 grid, "
+                        "seed 4",
+            "pairs": pairs, "merge_steps": steps,
+            "plain_ms": ms_plain, "plain_pairs_per_s": pairs / (ms_plain * 1e-3),
+            "batched_ms": ms_batch, "batched_pairs_per_s": pairs / (ms_batch * 1e-3),
+            "speedup": ms_plain / ms_batch,
+            "plans": [f"{s}/q{q}" for s, q in classes]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[1])
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +155,9 @@ def main() -> int:
     ap.add_argument("--q", type=int, default=0, help="tile edge (default 8)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--plain-only", action="store_true", help="time only the plain form")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven-batch comparison (256 matrices)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the measurement, copy this many MiB device to device once "
                          "(a plain copy kernel of known size to scale HBM byte counters)")
@@ -159,9 +212,32 @@ def main() -> int:
     st = K.ktau_status(ws)
     if st != K.KTAU_OK:
         raise RuntimeError(f"device status {st}")
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_plain = (t1 - t0) * 1e3 / args.steps
     prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
     pair_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+
+    # the batched form of the same workload: a one-matrix plan (persistent
+    # kernel, autotuned scheme, hipGraph), writing the same output arrays
+    batched = None
+    if not args.plain_only:
+        plan = K.KtauBatch([Xd], outs=[out], stream=stream)
+        for _ in range(max(1, args.warmup)):
+            plan.run(stream)
+        torch.cuda.synchronize()
+        if plan.status(stream) != K.KTAU_OK:
+            raise RuntimeError("batched warm-up failed")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.run(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if plan.status(stream) != K.KTAU_OK:
+            raise RuntimeError("batched run failed")
+        ms_batched = (t1 - t0) * 1e3 / args.steps
+        batched = {"ms_per_step": ms_batched, "pairs_per_s": P / (ms_batched * 1e-3),
+                   "scheme": plan.plan(0)[0], "q": plan.plan(0)[1]}
+        plan.close()
+    ms_step = ms_plain if batched is None else batched["ms_per_step"]
 
     steps_per_pair = merge_steps(n)
     ops_per_launch = P * steps_per_pair
@@ -186,12 +262,13 @@ def main() -> int:
         "config": {
             "workload": "allpairs m=16384 n=1024 log-normal, blocks of 64 rows at rho=0.6, "
                         "2% exact zeros, seed 3",
-            "m": m, "n": n, "pairs": P, "form": "plain",
-            "scheme": K.ktau_scheme_names()[scheme], "q": args.q or 8,
+            "m": m, "n": n, "pairs": P, "form": "plain" if batched is None else "batched",
             "input_sha256": synth.sha256(X)[:16],
         },
-        "prepass_ms": prep_ms,
-        "pair_kernel_ms": pair_ms,
+        "plain": {"ms_per_step": ms_plain, "pairs_per_s": P / (ms_plain * 1e-3),
+                  "scheme": K.ktau_scheme_names()[scheme], "q": args.q or 8,
+                  "prepass_ms": prep_ms, "pair_kernel_ms": pair_ms},
+        "batched": batched,
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -204,6 +281,8 @@ def main() -> int:
             "source_hash": src_hash,
         },
     }
+    if not args.no_uneven:
+        result["uneven_batch"] = uneven_batch(K, synth, torch, stream, max(2, args.steps))
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(X, args.cpu_seconds)
     print(json.dumps(result), flush=True)
