@@ -222,6 +222,119 @@ void ktau_batch_destroy(ktau_batch* plan);
 int ktau_autotune(const int64_t* ns_host, int64_t count, const char* cache_path,
                   void* stream, int32_t* schemes_out_host, int32_t* q_out_host);
 
+/* ---------------------------------------------------------------------------
+ * Query-vs-database search (Sec. 1: select the subject rows of a database
+ * that are co-expressed with a query row, ranking query-subject pairs by
+ * their score).  The score is tau_B; results are the k database rows of
+ * largest |tau_B| per query, ordered by |tau_B| descending then row index
+ * ascending; rows whose tau_B is NaN (a constant row) are never returned;
+ * missing results are idx -1, tau NaN, nd -1.
+ * ------------------------------------------------------------------------- */
+
+#define KTAU_MAX_K 1024
+
+typedef struct ktau_db ktau_db;   /* opaque: ranked database resident in HBM */
+
+/* Ranks the m x n database X_dev once into library-owned device memory
+ * (about 6 m ceil64(n) bytes); X_dev may be freed afterwards.  Synchronises
+ * `stream`; KTAU_ENAN if X_dev holds a NaN. */
+int ktau_db_create(const float* X_dev, int64_t m, int64_t n, void* stream,
+                   ktau_db** db_out);
+void ktau_db_destroy(ktau_db* db);
+int64_t ktau_db_rows(const ktau_db* db);
+int64_t ktau_db_samples(const ktau_db* db);
+
+/* Device workspace bytes of a ktau_query call with nq query rows. */
+size_t ktau_query_workspace_size(const ktau_db* db, int64_t nq, int64_t k);
+
+/* nq query rows Q_dev (nq x n float32, n = the database's) against every
+ * database row.  idx_out[nq*k] (int64), tau_out[nq*k] (double, signed
+ * tau_B) and nd_out[nq*k] (int64 n_d) are device arrays; tau_out and nd_out
+ * may be NULL.  Stream-ordered; a NaN query is latched in the workspace
+ * header (ktau_status). */
+int ktau_query(const ktau_db* db, const float* Q_dev, int64_t nq, int64_t k,
+               int64_t* idx_out_dev, double* tau_out_dev, int64_t* nd_out_dev,
+               void* workspace_dev, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Query server: continuous batching over a resident database.
+ *
+ * Requests (1..many query rows each, a k each) are queued in arrival order by
+ * ktau_server_submit and served by a worker thread inside the library.  When
+ * a slot (a stream) is free, the worker forms a launch from the head of the
+ * queue -- the head and the requests right behind it with the same k, up to
+ * max_batch_queries rows -- and admits it only if its device memory fits in
+ * what is left of the mem_budget_bytes pool; otherwise it waits until
+ * running launches complete.  Launches on different slots overlap on the
+ * device.  Each request's results are identical whether it ran alone or
+ * merged with others.  Latency = completion minus submission (queueing
+ * included).  Intended for callers that cannot wait on the device: all calls
+ * take and return host memory.
+ * ------------------------------------------------------------------------- */
+
+typedef struct ktau_server ktau_server;
+
+typedef struct ktau_server_cfg {
+  int32_t slots;             /* concurrent launches (streams); default 4        */
+  int32_t max_batch_queries; /* rows merged into one launch; default 64         */
+  int64_t mem_budget_bytes;  /* device pool for running launches; default 1 GiB */
+  int32_t max_queue;         /* queued requests before submit blocks/refuses    */
+  int32_t k_max;             /* largest k accepted; default 128 (<= KTAU_MAX_K) */
+} ktau_server_cfg;
+
+typedef struct ktau_latency {
+  double queue_us;           /* submission -> launch                           */
+  double device_us;          /* launch -> results on the host                  */
+  double total_us;           /* submission -> results on the host              */
+  int64_t batch_queries;     /* rows in the launch that served the request     */
+  int64_t batch_requests;    /* requests merged into that launch               */
+} ktau_latency;
+
+typedef struct ktau_server_stats {
+  int64_t launches, merged_requests, completed, failed;
+  int64_t peak_pool_bytes, peak_running, queued;
+} ktau_server_counters;
+
+void ktau_server_default_cfg(ktau_server_cfg* cfg_host);
+
+/* Starts a server over `db` (which must outlive it) on the current device;
+ * allocates the pool and per-slot pinned staging. */
+int ktau_server_create(const ktau_db* db, const ktau_server_cfg* cfg_host,
+                       ktau_server** server_out);
+
+/* Queues nq query rows (q_host: nq x n float32, copied before returning) for
+ * top-k.  KTAU_ENAN for NaN rows, KTAU_ENOMEM if the request can never fit
+ * the pool, KTAU_EBUSY if the queue is full and blocking == 0 (blocking != 0
+ * waits for room).  *ticket_out identifies the request. */
+int ktau_server_submit(ktau_server* server, const float* q_host, int64_t nq, int64_t k,
+                       int blocking, int64_t* ticket_out);
+
+/* Waits (timeout_ms < 0: forever) for a request; on success copies nq*k
+ * results into idx_host / tau_host / nd_host (any may be NULL) and its
+ * latency into lat_host, and forgets the ticket.  Returns the request's
+ * status: KTAU_OK, KTAU_ECANCELED (cancelled or failed in its launch),
+ * KTAU_ETIMEDOUT (still pending; the ticket stays valid). */
+int ktau_server_wait(ktau_server* server, int64_t ticket, int64_t* idx_host,
+                     double* tau_host, int64_t* nd_host, ktau_latency* lat_host,
+                     int64_t timeout_ms);
+
+/* Removes a request that has not been launched yet (KTAU_EBUSY otherwise). */
+int ktau_server_cancel(ktau_server* server, int64_t ticket);
+
+/* Failure drill: a queued request is launched alone and completes with
+ * KTAU_ECANCELED without touching the device (KTAU_EBUSY if not queued). */
+int ktau_server_inject_failure(ktau_server* server, int64_t ticket);
+
+int ktau_server_stats(ktau_server* server, ktau_server_counters* stats_host);
+
+/* Device pool bytes one launch of nq rows with this k takes (0 if invalid),
+ * for sizing mem_budget_bytes. */
+size_t ktau_server_launch_bytes(const ktau_server* server, int64_t nq, int64_t k);
+
+/* Serves everything already queued, then stops the worker and frees the
+ * server. */
+void ktau_server_destroy(ktau_server* server);
+
 #ifdef __cplusplus
 }
 #endif

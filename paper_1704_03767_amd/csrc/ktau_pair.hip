@@ -19,190 +19,10 @@
 // bitonic network of ktau_bitonic.h.  The composite pass uses an LDS merge
 // path with 32-bit keys.  Keeping it in its own kernel keeps the register
 // budget of the main kernels small.
-#include "ktau_bitonic.h"
-#include "ktau_internal.h"
+#include "ktau_pairdev.h"
 
 namespace ktau {
 namespace {
-
-constexpr int kBlock = 256;      // threads per workgroup for every pair kernel
-constexpr int kWavesPerBlock = kBlock / 64;
-
-// ---------------------------------------------------------------- utilities
-
-template <int G>
-__device__ __forceinline__ void group_sync() {
-  if constexpr (G == 64) {
-    // one wave: LDS operations of a wave complete in order; this only stops
-    // the compiler from moving LDS accesses across the point
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
-}
-
-// Sum over the group; every lane gets the total.
-template <int G>
-__device__ __forceinline__ uint32_t group_sum(uint32_t v, uint32_t* red) {
-  v = wave_sum(v);
-  if constexpr (G == 64) {
-    return v;
-  } else {
-    const int wave = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[wave] = v;
-    __syncthreads();
-    uint32_t t = 0;
-#pragma unroll
-    for (int w = 0; w < G / 64; ++w) t += red[w];
-    return t;
-  }
-}
-
-// K consecutive uint16 from a 2K-byte aligned address, by vector loads.
-template <int K>
-__device__ __forceinline__ void load_u16(const uint16_t* p, uint16_t (&out)[K]) {
-  if constexpr (K == 2) {
-    const uint32_t w = *(const uint32_t*)p;
-    out[0] = (uint16_t)w;
-    out[1] = (uint16_t)(w >> 16);
-  } else if constexpr (K == 4) {
-    const uint2 w = *(const uint2*)p;
-    out[0] = (uint16_t)w.x;
-    out[1] = (uint16_t)(w.x >> 16);
-    out[2] = (uint16_t)w.y;
-    out[3] = (uint16_t)(w.y >> 16);
-  } else {
-#pragma unroll
-    for (int i = 0; i < K / 8; ++i) {
-      const uint4 w = ((const uint4*)p)[i];
-      const uint32_t a[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        out[8 * i + 2 * c] = (uint16_t)a[c];
-        out[8 * i + 2 * c + 1] = (uint16_t)(a[c] >> 16);
-      }
-    }
-  }
-}
-
-template <int K>
-__device__ __forceinline__ void store_u16(uint16_t* p, const uint16_t (&in)[K]) {
-#pragma unroll
-  for (int i = 0; i < K / 2; ++i)
-    ((uint32_t*)p)[i] = (uint32_t)in[2 * i] | ((uint32_t)in[2 * i + 1] << 16);
-}
-
-// Step 5 and Eq. 1/3: store the counts and tau of job slot `slot`.
-__device__ __forceinline__ void store_pair(const PairOut& o, int64_t slot, int64_t n, int64_t n1y,
-                                           int64_t n1x, uint32_t nd32, uint32_t n332) {
-  const int64_t n0 = n * (n - 1) / 2;
-  const int64_t nd = nd32, n3 = n332;
-  const int64_t nc = n0 - n1y - n1x + n3 - nd;
-  if (o.nc) o.nc[slot] = nc;
-  if (o.nd) o.nd[slot] = nd;
-  if (o.n3) o.n3[slot] = n3;
-  const double num = (double)(nc - nd);
-  if (o.tau_b) {
-    const double d1 = (double)(n0 - n1y);
-    const double d2 = (double)(n0 - n1x);
-    const double prod = d1 * d2;
-    const double den = sqrt(prod);
-    o.tau_b[slot] = den == 0.0 ? __builtin_nan("") : num / den;
-  }
-  if (o.tau_a) o.tau_a[slot] = num / (double)n0;
-}
-
-// ======================================================= main (fast) path
-
-// LDS words per group: the v rank row (uint16), reused for v' on the tie
-// path, plus the network's exchange buffer for 256-lane groups.
-template <int K, int G>
-struct FastLds {
-  static constexpr int kRowWords = K * G / 2;
-  static constexpr int kXWords = G == 256 ? (K / 2) * 256 : 0;
-  static constexpr int kWords = kRowWords + kXWords + 16;
-};
-
-// n_d and n3 of rows (y, x) unless both rows exceed the tie budget (then
-// returns false and the composite pass handles the pair).  Called by every
-// lane of the group with the same arguments.
-template <int K, int G>
-__device__ __forceinline__ bool pair_fast(const RankView& rv, int64_t y, int64_t x, int n,
-                                          int64_t budget, uint32_t* lds, uint32_t* red, int lane,
-                                          uint32_t& nd, uint32_t& n3) {
-  using FL = FastLds<K, G>;
-  using Net = bitonic::Net<K, G>;
-  const int64_t n1y = rv.n1[y], n1x = rv.n1[x];
-  if (n1y > budget && n1x > budget) return false;
-  int64_t u = y, v = x, n1u = n1y;
-  if (n1x < n1y) {
-    u = x;
-    v = y;
-    n1u = n1x;
-  }
-  const int k0 = lane * K;
-  const bool in_row = k0 + K <= rv.ld;           // vector loads stay inside the row
-  uint16_t* row = (uint16_t*)lds;
-  uint32_t* xbuf = lds + FL::kRowWords;
-  // stage v's rank row in LDS
-  {
-    uint16_t r[K];
-    if (in_row) {
-      load_u16<K>(rv.rank + v * rv.ld + k0, r);
-      store_u16<K>(row + k0, r);
-    }
-  }
-  uint16_t p[K];
-  if (in_row) load_u16<K>(rv.perm + u * rv.ld + k0, p);
-  group_sync<G>();
-  uint32_t key[K];
-#pragma unroll
-  for (int r = 0; r < K; ++r) key[r] = (k0 + r < n) ? (uint32_t)row[p[r]] : 0x7FFFu;
-  uint32_t xin = 0, tie = 0;
-  if (n1u != 0) {
-    // v' in u order replaces the rank row once every lane has gathered
-    group_sync<G>();
-    {
-      uint16_t kv[K];
-#pragma unroll
-      for (int r = 0; r < K; ++r) kv[r] = (uint16_t)key[r];
-      if (in_row) store_u16<K>(row + k0, kv);
-    }
-    group_sync<G>();
-    // positions up to the end of u's last tie run, spread over lanes with
-    // stride G so that one run is shared by many lanes; each is compared
-    // with the earlier positions of its run
-    const uint16_t* ru = rv.rstart + u * rv.ld;
-    const int end = rv.tie_end[u];
-    for (int k = lane; k < end; k += G) {
-      const int s = ru[k];
-      const uint32_t me = row[k];
-      for (int j = s; j < k; ++j) {
-        const uint32_t o = row[j];
-        xin += o > me ? 1u : 0u;
-        tie += o == me ? 1u : 0u;
-      }
-    }
-  }
-  const uint32_t inv = group_sum<G>(Net::count(key, lane, xbuf), red);
-  if (n1u != 0) {
-    nd = inv - group_sum<G>(xin, red);
-    n3 = group_sum<G>(tie, red);
-  } else {
-    nd = inv;
-    n3 = 0;
-  }
-  return true;
-}
 
 // One q x q tile (Eq. 11-14) of a matrix; its pairs go to the waves
 // round-robin (G = 64) or one after another to the whole workgroup (G = 256).
@@ -221,7 +41,7 @@ __device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t t, uint32_t
     const int64_t y = yq * q + p / q, x = xq * q + p % q;
     if (y >= x || x >= d.m) continue;
     uint32_t nd, n3;
-    if (pair_fast<K, G>(d.rv, y, x, d.n, budget, lds, red, lane, nd, n3) && lane == 0)
+    if (pair_fast<K, G>(d.rv, y, d.rv, x, d.n, budget, lds, red, lane, nd, n3) && lane == 0)
       store_pair(d.out, strict_job(d.m, y, x), d.n, d.rv.n1[y], d.rv.n1[x], nd, n3);
   }
 }
@@ -252,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) pairs_jobs_kernel(MatDesc d) {
     int64_t y, x;
     strict_pair(d.m, d.J_begin + i, y, x);
     uint32_t nd, n3;
-    if (pair_fast<K, G>(d.rv, y, x, d.n, budget, buf, red, lane, nd, n3) && lane == 0)
+    if (pair_fast<K, G>(d.rv, y, d.rv, x, d.n, budget, buf, red, lane, nd, n3) && lane == 0)
       store_pair(d.out, i, d.n, d.rv.n1[y], d.rv.n1[x], nd, n3);
   }
 }
@@ -327,152 +147,6 @@ __global__ void __launch_bounds__(kBlock) heavy_batch_kernel(const MatDesc* desc
   heavy_rows(d);
 }
 
-// ============================================ composite pass (LDS merge)
-
-// In-lane: strict inversions among the lane's K keys, then a bitonic sorting
-// network leaves them ascending (indices are compile-time, keys stay in
-// registers).
-template <int K>
-__device__ __forceinline__ uint32_t lane_sort_count(uint32_t (&key)[K]) {
-  uint32_t c = 0;
-#pragma unroll
-  for (int i = 0; i < K; ++i)
-#pragma unroll
-    for (int j = i + 1; j < K; ++j) c += key[i] > key[j] ? 1u : 0u;
-#pragma unroll
-  for (int size = 2; size <= K; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool up = (i & size) == 0;
-          uint32_t a = key[i], b = key[j];
-          uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-          key[i] = up ? lo : hi;
-          key[j] = up ? hi : lo;
-        }
-      }
-    }
-  }
-  return c;
-}
-
-// buf holds 2*G*K + 16 keys.  On entry every lane's K keys are sorted; on exit
-// the group's keys are sorted (lane-blocked) and the return value is this
-// lane's share of the cross-lane inversions (Algorithm 2: a right-run key
-// taken before left-run keys adds the number of left keys still waiting).
-template <int K, int G>
-__device__ __forceinline__ uint32_t merge_levels(uint32_t (&key)[K], uint32_t* buf, int lane) {
-  constexpr int N = G * K;
-  uint32_t cnt = 0;
-  int cur = 0;
-#pragma unroll 1
-  for (int s = K; s < N; s <<= 1) {
-    uint32_t* b = buf + cur * N;
-#pragma unroll
-    for (int r = 0; r < K; ++r) b[lane * K + r] = key[r];
-    group_sync<G>();
-    const int pos = lane * K;
-    const int l0 = pos & ~(2 * s - 1);
-    const int diag = pos - l0;
-    const uint32_t* A = b + l0;
-    // merge path: number of A keys among the first `diag` outputs, A first
-    // on equal keys
-    int lo = diag > s ? diag - s : 0;
-    int hi = diag < s ? diag : s;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (A[mid] <= A[s + diag - 1 - mid]) lo = mid + 1;
-      else hi = mid;
-    }
-    int ia = lo, ib = diag - lo;
-    uint32_t a = ia < s ? A[ia] : kSentinel;
-    uint32_t bb = ib < s ? A[s + ib] : kSentinel;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const bool takeB = bb < a;   // strict: equal keys are not discordant
-      key[t] = takeB ? bb : a;
-      cnt += takeB ? (uint32_t)(s - ia) : 0u;
-      ia += takeB ? 0 : 1;
-      ib += takeB ? 1 : 0;
-      const int idx = takeB ? ib : ia;
-      const uint32_t raw = A[takeB ? s + ib : ia];
-      const uint32_t nv = idx < s ? raw : kSentinel;
-      a = takeB ? a : nv;
-      bb = takeB ? nv : bb;
-    }
-    cur ^= 1;
-  }
-  return cnt;
-}
-
-template <int K, int G>
-__device__ __forceinline__ uint32_t sort_count(uint32_t (&key)[K], uint32_t* buf, int lane,
-                                               uint32_t* red) {
-  uint32_t c = lane_sort_count<K>(key);
-  c += merge_levels<K, G>(key, buf, lane);
-  return group_sum<G>(c, red);
-}
-
-template <int K, int G>
-struct CompLds {
-  static constexpr int kWords = 2 * G * K + 16;
-};
-
-// Both rows heavy: Step 1 literally (sort by (u run, v')), joint ties from
-// equal composite keys, then Step 3 on v' alone.
-template <int K, int G>
-__device__ void pair_composite(const RankView& rv, int64_t y, int64_t x, int n, uint32_t* buf,
-                               uint32_t* red, int lane, uint32_t& nd, uint32_t& n3) {
-  const int64_t n1y = rv.n1[y], n1x = rv.n1[x];
-  int64_t u = y, v = x;
-  if (n1x < n1y) {
-    u = x;
-    v = y;
-  }
-  const uint16_t* pu = rv.perm + u * rv.ld;
-  const uint16_t* rk = rv.rank + v * rv.ld;
-  const uint16_t* ru = rv.rstart + u * rv.ld;
-  const int k0 = lane * K;
-  uint32_t key[K];
-#pragma unroll
-  for (int r = 0; r < K; ++r) {
-    const int k = k0 + r;
-    key[r] = k < n ? ((uint32_t)ru[k] << 16) | (uint32_t)rk[pu[k]] : kPadKey;
-  }
-  (void)sort_count<K, G>(key, buf, lane, red);
-  // joint ties: in the (u, v)-sorted sequence, sum over positions of the
-  // number of earlier positions holding an equal composite key.  The last
-  // merge level (log2 G of them, an even number) read region 1, so region 0
-  // is free.
-  uint32_t* sb = buf;
-#pragma unroll
-  for (int r = 0; r < K; ++r) sb[k0 + r] = key[r];
-  group_sync<G>();
-  uint32_t tie = 0;
-#pragma unroll
-  for (int r = 0; r < K; ++r) {
-    const int k = k0 + r;
-    if (k < n) {
-      int lo = 0, hi = k;   // first position holding a key equal to key[r]
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (sb[mid] < key[r]) lo = mid + 1;
-        else hi = mid;
-      }
-      tie += (uint32_t)(k - lo);
-    }
-  }
-  n3 = group_sum<G>(tie, red);
-#pragma unroll
-  for (int r = 0; r < K; ++r)
-    if (key[r] != kPadKey) key[r] &= 0xFFFFu;
-  group_sync<G>();
-  nd = sort_count<K, G>(key, buf, lane, red);
-}
-
 // Every pair of heavy rows of one matrix, grid-strided over its heavy
 // sub-triangle; results land at the pair's job slot if it is in range.
 template <int K, int G>
@@ -491,7 +165,7 @@ __device__ void composite_matrix(const MatDesc& d, uint32_t* lds_all, uint32_t* 
     const int64_t J = strict_job(d.m, y, x);
     if (J < d.J_begin || J >= d.J_end) continue;
     uint32_t nd, n3;
-    pair_composite<K, G>(d.rv, y, x, d.n, buf, red, lane, nd, n3);
+    pair_composite<K, G>(d.rv, y, d.rv, x, d.n, buf, red, lane, nd, n3);
     if (lane == 0) store_pair(d.out, J - d.J_begin, d.n, d.rv.n1[y], d.rv.n1[x], nd, n3);
   }
 }
@@ -637,6 +311,11 @@ hipError_t launch_pairs_persistent(int scheme, const MatDesc* d, int64_t count, 
     case kBlockK16: return persistent_t<16, 256>(d, count, total, prefix, counter, status, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_heavy(const MatDesc& d, hipStream_t s) {
+  hipLaunchKernelGGL(heavy_plain_kernel, dim3(1), dim3(kBlock), 0, s, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, hipStream_t s) {

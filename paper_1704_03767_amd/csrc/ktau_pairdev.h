@@ -1,0 +1,341 @@
+// Device routines shared by the pair kernels of every form (all-pairs,
+// batched, query-vs-database): group primitives, the per-pair fast path
+// (tagged bitonic count with the direct in-run tie correction), the
+// composite path for two heavily tied rows, and the Step 5 / Eq. 1, 3 store.
+// Internal to libktau.
+#pragma once
+
+#include "ktau_bitonic.h"
+#include "ktau_internal.h"
+
+namespace ktau {
+namespace {
+
+constexpr int kBlock = 256;      // threads per workgroup for every pair kernel
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// ---------------------------------------------------------------- utilities
+
+template <int G>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (G == 64) {
+    // one wave: LDS operations of a wave complete in order; this only stops
+    // the compiler from moving LDS accesses across the point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Sum over the group; every lane gets the total.
+template <int G>
+__device__ __forceinline__ uint32_t group_sum(uint32_t v, uint32_t* red) {
+  v = wave_sum(v);
+  if constexpr (G == 64) {
+    return v;
+  } else {
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < G / 64; ++w) t += red[w];
+    return t;
+  }
+}
+
+// K consecutive uint16 from a 2K-byte aligned address, by vector loads.
+template <int K>
+__device__ __forceinline__ void load_u16(const uint16_t* p, uint16_t (&out)[K]) {
+  if constexpr (K == 2) {
+    const uint32_t w = *(const uint32_t*)p;
+    out[0] = (uint16_t)w;
+    out[1] = (uint16_t)(w >> 16);
+  } else if constexpr (K == 4) {
+    const uint2 w = *(const uint2*)p;
+    out[0] = (uint16_t)w.x;
+    out[1] = (uint16_t)(w.x >> 16);
+    out[2] = (uint16_t)w.y;
+    out[3] = (uint16_t)(w.y >> 16);
+  } else {
+#pragma unroll
+    for (int i = 0; i < K / 8; ++i) {
+      const uint4 w = ((const uint4*)p)[i];
+      const uint32_t a[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        out[8 * i + 2 * c] = (uint16_t)a[c];
+        out[8 * i + 2 * c + 1] = (uint16_t)(a[c] >> 16);
+      }
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void store_u16(uint16_t* p, const uint16_t (&in)[K]) {
+#pragma unroll
+  for (int i = 0; i < K / 2; ++i)
+    ((uint32_t*)p)[i] = (uint32_t)in[2 * i] | ((uint32_t)in[2 * i + 1] << 16);
+}
+
+// Step 5 and Eq. 1/3: store the counts and tau of job slot `slot`.
+__device__ __forceinline__ void store_pair(const PairOut& o, int64_t slot, int64_t n, int64_t n1y,
+                                           int64_t n1x, uint32_t nd32, uint32_t n332) {
+  const int64_t n0 = n * (n - 1) / 2;
+  const int64_t nd = nd32, n3 = n332;
+  const int64_t nc = n0 - n1y - n1x + n3 - nd;
+  if (o.nc) o.nc[slot] = nc;
+  if (o.nd) o.nd[slot] = nd;
+  if (o.n3) o.n3[slot] = n3;
+  const double num = (double)(nc - nd);
+  if (o.tau_b) {
+    const double d1 = (double)(n0 - n1y);
+    const double d2 = (double)(n0 - n1x);
+    const double prod = d1 * d2;
+    const double den = sqrt(prod);
+    o.tau_b[slot] = den == 0.0 ? __builtin_nan("") : num / den;
+  }
+  if (o.tau_a) o.tau_a[slot] = num / (double)n0;
+}
+
+// ======================================================= main (fast) path
+
+// LDS words per group: the v rank row (uint16), reused for v' on the tie
+// path, plus the network's exchange buffer for 256-lane groups.
+template <int K, int G>
+struct FastLds {
+  static constexpr int kRowWords = K * G / 2;
+  static constexpr int kXWords = G == 256 ? (K / 2) * 256 : 0;
+  static constexpr int kWords = kRowWords + kXWords + 16;
+};
+
+// n_d and n3 of rows (y, x) unless both rows exceed the tie budget (then
+// returns false and the composite pass handles the pair).  Called by every
+// lane of the group with the same arguments.
+template <int K, int G>
+__device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const RankView& rx,
+                                          int64_t x, int n, int64_t budget, uint32_t* lds,
+                                          uint32_t* red, int lane, uint32_t& nd, uint32_t& n3) {
+  using FL = FastLds<K, G>;
+  using Net = bitonic::Net<K, G>;
+  const int64_t n1y = ry.n1[y], n1x = rx.n1[x];
+  if (n1y > budget && n1x > budget) return false;
+  // u: the row with fewer ties; both views share the row stride
+  const bool swap = n1x < n1y;
+  const RankView& ru_v = swap ? rx : ry;
+  const RankView& rv_v = swap ? ry : rx;
+  const int64_t u = swap ? x : y, v = swap ? y : x;
+  const int64_t n1u = swap ? n1x : n1y;
+  const int64_t ld = ry.ld;
+  const int k0 = lane * K;
+  const bool in_row = k0 + K <= ld;              // vector loads stay inside the row
+  uint16_t* row = (uint16_t*)lds;
+  uint32_t* xbuf = lds + FL::kRowWords;
+  // stage v's rank row in LDS
+  {
+    uint16_t r[K];
+    if (in_row) {
+      load_u16<K>(rv_v.rank + v * ld + k0, r);
+      store_u16<K>(row + k0, r);
+    }
+  }
+  uint16_t p[K];
+  if (in_row) load_u16<K>(ru_v.perm + u * ld + k0, p);
+  group_sync<G>();
+  uint32_t key[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) key[r] = (k0 + r < n) ? (uint32_t)row[p[r]] : 0x7FFFu;
+  uint32_t xin = 0, tie = 0;
+  if (n1u != 0) {
+    // v' in u order replaces the rank row once every lane has gathered
+    group_sync<G>();
+    {
+      uint16_t kv[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) kv[r] = (uint16_t)key[r];
+      if (in_row) store_u16<K>(row + k0, kv);
+    }
+    group_sync<G>();
+    // positions up to the end of u's last tie run, spread over lanes with
+    // stride G so that one run is shared by many lanes; each is compared
+    // with the earlier positions of its run
+    const uint16_t* ru = ru_v.rstart + u * ld;
+    const int end = ru_v.tie_end[u];
+    for (int k = lane; k < end; k += G) {
+      const int s = ru[k];
+      const uint32_t me = row[k];
+      for (int j = s; j < k; ++j) {
+        const uint32_t o = row[j];
+        xin += o > me ? 1u : 0u;
+        tie += o == me ? 1u : 0u;
+      }
+    }
+  }
+  const uint32_t inv = group_sum<G>(Net::count(key, lane, xbuf), red);
+  if (n1u != 0) {
+    nd = inv - group_sum<G>(xin, red);
+    n3 = group_sum<G>(tie, red);
+  } else {
+    nd = inv;
+    n3 = 0;
+  }
+  return true;
+}
+
+// ============================================ composite pass (LDS merge)
+
+// In-lane: strict inversions among the lane's K keys, then a bitonic sorting
+// network leaves them ascending (indices are compile-time, keys stay in
+// registers).
+template <int K>
+__device__ __forceinline__ uint32_t lane_sort_count(uint32_t (&key)[K]) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = i + 1; j < K; ++j) c += key[i] > key[j] ? 1u : 0u;
+#pragma unroll
+  for (int size = 2; size <= K; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool up = (i & size) == 0;
+          uint32_t a = key[i], b = key[j];
+          uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+          key[i] = up ? lo : hi;
+          key[j] = up ? hi : lo;
+        }
+      }
+    }
+  }
+  return c;
+}
+
+// buf holds 2*G*K + 16 keys.  On entry every lane's K keys are sorted; on exit
+// the group's keys are sorted (lane-blocked) and the return value is this
+// lane's share of the cross-lane inversions (Algorithm 2: a right-run key
+// taken before left-run keys adds the number of left keys still waiting).
+template <int K, int G>
+__device__ __forceinline__ uint32_t merge_levels(uint32_t (&key)[K], uint32_t* buf, int lane) {
+  constexpr int N = G * K;
+  uint32_t cnt = 0;
+  int cur = 0;
+#pragma unroll 1
+  for (int s = K; s < N; s <<= 1) {
+    uint32_t* b = buf + cur * N;
+#pragma unroll
+    for (int r = 0; r < K; ++r) b[lane * K + r] = key[r];
+    group_sync<G>();
+    const int pos = lane * K;
+    const int l0 = pos & ~(2 * s - 1);
+    const int diag = pos - l0;
+    const uint32_t* A = b + l0;
+    // merge path: number of A keys among the first `diag` outputs, A first
+    // on equal keys
+    int lo = diag > s ? diag - s : 0;
+    int hi = diag < s ? diag : s;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (A[mid] <= A[s + diag - 1 - mid]) lo = mid + 1;
+      else hi = mid;
+    }
+    int ia = lo, ib = diag - lo;
+    uint32_t a = ia < s ? A[ia] : kSentinel;
+    uint32_t bb = ib < s ? A[s + ib] : kSentinel;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const bool takeB = bb < a;   // strict: equal keys are not discordant
+      key[t] = takeB ? bb : a;
+      cnt += takeB ? (uint32_t)(s - ia) : 0u;
+      ia += takeB ? 0 : 1;
+      ib += takeB ? 1 : 0;
+      const int idx = takeB ? ib : ia;
+      const uint32_t raw = A[takeB ? s + ib : ia];
+      const uint32_t nv = idx < s ? raw : kSentinel;
+      a = takeB ? a : nv;
+      bb = takeB ? nv : bb;
+    }
+    cur ^= 1;
+  }
+  return cnt;
+}
+
+template <int K, int G>
+__device__ __forceinline__ uint32_t sort_count(uint32_t (&key)[K], uint32_t* buf, int lane,
+                                               uint32_t* red) {
+  uint32_t c = lane_sort_count<K>(key);
+  c += merge_levels<K, G>(key, buf, lane);
+  return group_sum<G>(c, red);
+}
+
+template <int K, int G>
+struct CompLds {
+  static constexpr int kWords = 2 * G * K + 16;
+};
+
+// Both rows heavy: Step 1 literally (sort by (u run, v')), joint ties from
+// equal composite keys, then Step 3 on v' alone.
+template <int K, int G>
+__device__ void pair_composite(const RankView& ry, int64_t y, const RankView& rx, int64_t x,
+                               int n, uint32_t* buf, uint32_t* red, int lane, uint32_t& nd,
+                               uint32_t& n3) {
+  const bool swap = rx.n1[x] < ry.n1[y];
+  const RankView& ru_v = swap ? rx : ry;
+  const RankView& rv_v = swap ? ry : rx;
+  const int64_t u = swap ? x : y, v = swap ? y : x;
+  const int64_t ld = ry.ld;
+  const uint16_t* pu = ru_v.perm + u * ld;
+  const uint16_t* rk = rv_v.rank + v * ld;
+  const uint16_t* ru = ru_v.rstart + u * ld;
+  const int k0 = lane * K;
+  uint32_t key[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    const int k = k0 + r;
+    key[r] = k < n ? ((uint32_t)ru[k] << 16) | (uint32_t)rk[pu[k]] : kPadKey;
+  }
+  (void)sort_count<K, G>(key, buf, lane, red);
+  // joint ties: in the (u, v)-sorted sequence, sum over positions of the
+  // number of earlier positions holding an equal composite key.  The last
+  // merge level (log2 G of them, an even number) read region 1, so region 0
+  // is free.
+  uint32_t* sb = buf;
+#pragma unroll
+  for (int r = 0; r < K; ++r) sb[k0 + r] = key[r];
+  group_sync<G>();
+  uint32_t tie = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    const int k = k0 + r;
+    if (k < n) {
+      int lo = 0, hi = k;   // first position holding a key equal to key[r]
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sb[mid] < key[r]) lo = mid + 1;
+        else hi = mid;
+      }
+      tie += (uint32_t)(k - lo);
+    }
+  }
+  n3 = group_sum<G>(tie, red);
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+    if (key[r] != kPadKey) key[r] &= 0xFFFFu;
+  group_sync<G>();
+  nd = sort_count<K, G>(key, buf, lane, red);
+}
+
+}  // namespace
+}  // namespace ktau
