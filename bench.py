@@ -146,6 +146,101 @@ def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
             "plans": [f"{s}/q{q}" for s, q in classes]}
 
 
+def serving(K, synth, torch, stream, seconds: float) -> dict:
+    """Query-vs-database search over a resident 20000 x 800 log-normal
+    database (seed 5): requests of 1-64 query rows, top-100 by |tau_B|.
+    Closed-loop saturation of the server, one plain ktau_query launch per
+    request for comparison, then Poisson arrivals at 0.5x and 0.8x saturation
+    with per-request latency = completion - submission (queueing included)."""
+    import threading
+
+    import numpy as np
+
+    from paper_1704_03767_amd import serve as S
+
+    k = 100
+    db = synth.database(20000, 800, 5)
+    kdb = S.KtauDb(torch.from_numpy(db.X).cuda(), stream=stream)
+    m = db.X.shape[0]
+    rng = np.random.default_rng(55)
+    pool_sizes = rng.integers(1, 65, 4096)
+    Qpool = synth.queries(db, int(pool_sizes.sum()), 56)
+    offs = np.concatenate([[0], np.cumsum(pool_sizes)])
+    req = [Qpool[offs[i]:offs[i + 1]] for i in range(len(pool_sizes))]
+
+    # plain: one stream-ordered launch per request, waited for
+    n_plain = 64
+    ws = torch.empty(S.ktau_query_workspace_size(kdb, 64, k), dtype=torch.uint8, device="cuda")
+    qdev = [torch.from_numpy(q).cuda() for q in req[:n_plain]]
+    S.ktau_query(kdb, qdev[0], k, ws, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in qdev:
+        S.ktau_query(kdb, q, k, ws, stream=stream, check=False)
+        stream.synchronize()
+    plain_s = time.perf_counter() - t0
+    plain_rows = int(sum(q.shape[0] for q in qdev))
+
+    srv = S.KtauServer(kdb)
+    # closed loop: everything submitted at once
+    n_sat = 256
+    for q in req[:8]:
+        srv.wait(srv.submit(q, k))
+    t0 = time.perf_counter()
+    tickets = [srv.submit(q, k) for q in req[:n_sat]]
+    for t in tickets:
+        st, _, _ = srv.wait(t)
+        if st != K.KTAU_OK:
+            raise RuntimeError(f"serving: request failed with {st}")
+    sat_s = time.perf_counter() - t0
+    sat_rows = int(sum(q.shape[0] for q in req[:n_sat]))
+    r_sat = n_sat / sat_s
+
+    def poisson(rate: float, seed: int) -> dict:
+        count = int(min(2000, max(100, rate * seconds)))
+        arrivals, _ = synth.poisson_requests(count, rate, seed)
+        order = [int(i) for i in rng.integers(0, len(req), count)]
+        tick = [None] * count
+        lat = [None] * count
+        t_start = time.perf_counter()
+
+        def submitter():
+            for i in range(count):
+                delay = t_start + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tick[i] = srv.submit(req[order[i]], k)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        for i in range(count):
+            while tick[i] is None:
+                time.sleep(0.0002)
+            st, _, l = srv.wait(tick[i])
+            if st != K.KTAU_OK:
+                raise RuntimeError(f"serving: request failed with {st}")
+            lat[i] = l
+        th.join()
+        wall = time.perf_counter() - t_start
+        tot = np.array([x["total_us"] for x in lat]) / 1e3
+        rows = sum(req[o].shape[0] for o in order)
+        return {"rate_rps": rate, "requests": count, "p50_ms": float(np.percentile(tot, 50)),
+                "p99_ms": float(np.percentile(tot, 99)), "mean_ms": float(tot.mean()),
+                "pairs_per_s": rows * m / wall,
+                "mean_batch_requests": float(np.mean([x["batch_requests"] for x in lat]))}
+
+    rates = [poisson(0.5 * r_sat, 57), poisson(0.8 * r_sat, 58)]
+    stats = srv.stats()
+    srv.close()
+    kdb.close()
+    return {"workload": "database 20000 x 800 log-normal (seed 5), requests of U{1..64} query "
+                        "rows (half near a database row), top-100 by |tau_B|, Poisson arrivals",
+            "plain_per_request_pairs_per_s": plain_rows * m / plain_s,
+            "plain_ms_per_request": plain_s * 1e3 / n_plain,
+            "saturation_rps": r_sat, "saturation_pairs_per_s": sat_rows * m / sat_s,
+            "at_rates": rates, "server": stats}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[1])
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +253,9 @@ def main() -> int:
     ap.add_argument("--plain-only", action="store_true", help="time only the plain form")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch comparison (256 matrices)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="target length of each Poisson run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the measurement, copy this many MiB device to device once "
                          "(a plain copy kernel of known size to scale HBM byte counters)")
@@ -283,6 +381,11 @@ def main() -> int:
     }
     if not args.no_uneven:
         result["uneven_batch"] = uneven_batch(K, synth, torch, stream, max(2, args.steps))
+    if not args.no_serve:
+        result["serving"] = serving(K, synth, torch, stream, args.serve_seconds)
+        rates = result["serving"]["at_rates"]
+        result["p50_ms"] = rates[-1]["p50_ms"]
+        result["p99_ms"] = rates[-1]["p99_ms"]
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(X, args.cpu_seconds)
     print(json.dumps(result), flush=True)
