@@ -69,6 +69,10 @@ struct Net {
     const uint32_t e = ((uint32_t)lane << LOGK) | ((uint32_t)h << LOGKV) | (uint32_t)j;
     return (e >> b) & 1u;
   }
+  // All ones in lanes whose bit lb is clear (the lower partner of a stage).
+  static __device__ __forceinline__ uint32_t lane_mask(int lane, int lb) {
+    return (uint32_t)(((lane >> lb) & 1) - 1);
+  }
   static __device__ __forceinline__ uint32_t half_mask(uint32_t lo, uint32_t hi) {
     return (lo ? 0xFFFFu : 0u) | (hi ? 0xFFFF0000u : 0u);
   }
@@ -95,12 +99,14 @@ struct Net {
     } else {
       constexpr int lb = k - LOGK;            // lane bit
       if constexpr (lb < 4) {
-        const bool lower = ((lane >> lb) & 1) == 0;
+        // the lower lane keeps the minimum; a bit mask in a VGPR selects it
+        // (no per-lane condition has to live in scalar registers)
+        const uint32_t keep_min = lane_mask(lane, lb);
 #pragma unroll
         for (int j = 0; j < KV; ++j) {
           const u16x2 p = vec(lane_xor<(1 << lb)>(bits(v[j])));
           const u16x2 mn = pmin(v[j], p), mx = pmax(v[j], p);
-          v[j] = lower ? mn : mx;
+          v[j] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
         }
       } else if constexpr (lb == 4 || lb == 5) {
         if constexpr (KV >= 2) {
@@ -141,12 +147,13 @@ struct Net {
             auto s = __builtin_amdgcn_permlane32_swap(a, a, false, false);
             part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
           }
+          const uint32_t keep_min = lane_mask(lane, lb);
           const u16x2 mn = pmin(v[0], vec(part)), mx = pmax(v[0], vec(part));
-          v[0] = lower ? mn : mx;
+          v[0] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
         }
       } else {
         // across the waves of a 256-lane group, through LDS
-        const bool lower = ((lane >> lb) & 1) == 0;
+        const uint32_t keep_min = lane_mask(lane, lb);
 #pragma unroll
         for (int j = 0; j < KV; ++j) xbuf[j * G + lane] = bits(v[j]);
         __syncthreads();
@@ -154,7 +161,7 @@ struct Net {
         for (int j = 0; j < KV; ++j) {
           const u16x2 p = vec(xbuf[j * G + (lane ^ (1 << lb))]);
           const u16x2 mn = pmin(v[j], p), mx = pmax(v[j], p);
-          v[j] = lower ? mn : mx;
+          v[j] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
         }
         __syncthreads();
       }
@@ -222,7 +229,10 @@ struct Net {
         cnt += t;
       }
       const uint32_t s = dsum + base * ((cnt & 0xFFFFu) + (cnt >> 16));
-      return desc ? s : 0u - s;
+      // +s for a complemented block, -s otherwise: (s ^ m) - m with m all ones
+      // negates, computed without a scalar condition mask
+      const uint32_t m = desc ? 0u : 0xFFFFFFFFu;
+      return (s ^ m) - m;
     }
   }
 

@@ -37,13 +37,16 @@ __device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t t, uint32_t
   tile_coord(d.w, t, yq, xq);
   const int q = d.q;
   const int64_t budget = direct_budget(d.n);
+  Deferred<G> done;
   for (int p = group; p < q * q; p += kGroups) {
     const int64_t y = yq * q + p / q, x = xq * q + p % q;
     if (y >= x || x >= d.m) continue;
     uint32_t nd, n3;
-    if (pair_fast<K, G>(d.rv, y, d.rv, x, d.n, budget, lds, red, lane, nd, n3) && lane == 0)
-      store_pair(d.out, strict_job(d.m, y, x), d.n, d.rv.n1[y], d.rv.n1[x], nd, n3);
+    if (!pair_fast<K, G>(d.rv, y, d.rv, x, d.n, budget, lds, red, lane, nd, n3)) continue;
+    done.add(lane, strict_job(d.m, y, x), d.rv.n1[y], d.rv.n1[x], nd, n3);
+    if (done.full()) done.flush(lane, d.out, d.n);
   }
+  done.flush(lane, d.out, d.n);
 }
 
 // Plain launch, tile order.
@@ -67,14 +70,17 @@ __global__ void __launch_bounds__(kBlock) pairs_jobs_kernel(MatDesc d) {
   uint32_t* buf = lds + group * FastLds<K, G>::kWords;
   const int64_t count = d.J_end - d.J_begin;
   const int64_t budget = direct_budget(d.n);
+  Deferred<G> done;
   for (int64_t i = (int64_t)blockIdx.x * kGroups + group; i < count;
        i += (int64_t)gridDim.x * kGroups) {
     int64_t y, x;
     strict_pair(d.m, d.J_begin + i, y, x);
     uint32_t nd, n3;
-    if (pair_fast<K, G>(d.rv, y, d.rv, x, d.n, budget, buf, red, lane, nd, n3) && lane == 0)
-      store_pair(d.out, i, d.n, d.rv.n1[y], d.rv.n1[x], nd, n3);
+    if (!pair_fast<K, G>(d.rv, y, d.rv, x, d.n, budget, buf, red, lane, nd, n3)) continue;
+    done.add(lane, i, d.rv.n1[y], d.rv.n1[x], nd, n3);
+    if (done.full()) done.flush(lane, d.out, d.n);
   }
+  done.flush(lane, d.out, d.n);
 }
 
 // Persistent launch over the concatenated tile spaces of the matrices of one
@@ -231,7 +237,7 @@ hipError_t launch_jobs_t(const MatDesc& d, hipStream_t s) {
   constexpr int kGroups = kBlock / G;
   int64_t count = d.J_end - d.J_begin;
   int64_t grid = (count + kGroups - 1) / kGroups;
-  if (grid > (1ll << 30)) grid = 1ll << 30;
+  if (grid > kMaxPairGrid) grid = kMaxPairGrid;
   if (grid < 1) return hipSuccess;
   hipLaunchKernelGGL((pairs_jobs_kernel<K, G>), dim3((unsigned)grid), dim3(kBlock), 0, s, d);
   return hipGetLastError();

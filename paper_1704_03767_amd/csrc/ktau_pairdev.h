@@ -13,6 +13,8 @@ namespace {
 
 constexpr int kBlock = 256;      // threads per workgroup for every pair kernel
 constexpr int kWavesPerBlock = kBlock / 64;
+// Grid cap of the job-order launches (256 CUs x 32 workgroups).
+constexpr int64_t kMaxPairGrid = 8192;
 
 // ---------------------------------------------------------------- utilities
 
@@ -106,6 +108,37 @@ __device__ __forceinline__ void store_pair(const PairOut& o, int64_t slot, int64
   }
   if (o.tau_a) o.tau_a[slot] = num / (double)n0;
 }
+
+// Counts of up to G finished pairs of one group, one pair per lane, so that
+// the FP64 tau of Eq. 3 and the stores are issued once for all of them
+// instead of once per pair.
+template <int G>
+struct Deferred {
+  int cnt = 0;
+  int64_t slot = 0, n1y = 0, n1x = 0;
+  uint32_t nd = 0, n3 = 0;
+  __device__ __forceinline__ void add(int lane, int64_t s, int64_t a, int64_t b, uint32_t d,
+                                      uint32_t t) {
+    if (lane == cnt) {
+      slot = s;
+      n1y = a;
+      n1x = b;
+      nd = d;
+      n3 = t;
+    }
+    ++cnt;
+  }
+  __device__ __forceinline__ bool full() const { return cnt == G; }
+  __device__ __forceinline__ void flush(int lane, const PairOut& o, int64_t n) {
+    if (lane < cnt) store_pair(o, slot, n, n1y, n1x, nd, n3);
+    cnt = 0;
+  }
+  template <class Store>
+  __device__ __forceinline__ void flush_with(int lane, Store&& store) {
+    if (lane < cnt) store(slot, n1y, n1x, nd, n3);
+    cnt = 0;
+  }
+};
 
 // ======================================================= main (fast) path
 

@@ -31,13 +31,19 @@ __global__ void __launch_bounds__(kBlock) query_pairs_kernel(QueryDesc qd) {
   uint32_t* buf = lds + group * FastLds<K, G>::kWords;
   const int64_t jobs = qd.nq * qd.m;
   const int64_t budget = direct_budget(qd.n);
+  Deferred<G> done;
+  auto store = [&](int64_t slot, int64_t a, int64_t b, uint32_t d, uint32_t t) {
+    store_cross(qd, slot, a, b, d, t);
+  };
   for (int64_t i = (int64_t)blockIdx.x * kGroups + group; i < jobs;
        i += (int64_t)gridDim.x * kGroups) {
     const int64_t qi = i / qd.m, j = i - qi * qd.m;
     uint32_t nd, n3;
-    if (pair_fast<K, G>(qd.rq, qi, qd.rdb, j, qd.n, budget, buf, red, lane, nd, n3) && lane == 0)
-      store_cross(qd, i, qd.rq.n1[qi], qd.rdb.n1[j], nd, n3);
+    if (!pair_fast<K, G>(qd.rq, qi, qd.rdb, j, qd.n, budget, buf, red, lane, nd, n3)) continue;
+    done.add(lane, i, qd.rq.n1[qi], qd.rdb.n1[j], nd, n3);
+    if (done.full()) done.flush_with(lane, store);
   }
+  done.flush_with(lane, store);
 }
 
 // Pairs of a heavy query row and a heavy database row.
@@ -160,8 +166,10 @@ template <int K, int G>
 hipError_t query_pairs_t(const QueryDesc& qd, hipStream_t s) {
   constexpr int kGroups = kBlock / G;
   const int64_t jobs = qd.nq * qd.m;
+  // enough workgroups to fill the device several times over, each group
+  // then finishing many pairs (their tau stores go out together)
   int64_t grid = (jobs + kGroups - 1) / kGroups;
-  if (grid > (1ll << 30)) grid = 1ll << 30;
+  if (grid > kMaxPairGrid) grid = kMaxPairGrid;
   if (grid < 1) return hipSuccess;
   hipLaunchKernelGGL((query_pairs_kernel<K, G>), dim3((unsigned)grid), dim3(kBlock), 0, s, qd);
   hipError_t e = hipGetLastError();
