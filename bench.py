@@ -86,10 +86,14 @@ def cpu_baseline(X, seconds: float, seed: int = 99) -> dict:
         oracle.pairs(X, ys, xs, "gse", threads)
         return time.perf_counter() - t0
 
-    probe = max(threads * 8, 256)
-    dt = run(probe)
-    count = int(max(probe, min(50_000_000, probe * seconds / max(dt, 1e-6))))
-    dt = run(count)
+    # batches of seeded pairs, each sized from the rate so far, until about
+    # `seconds` of oracle time have been spent
+    count, dt, batch = 0, 0.0, max(threads * 64, 1024)
+    while dt < seconds:
+        dt += run(batch)
+        count += batch
+        left = seconds - dt
+        batch = int(min(20_000_000, max(threads * 64, 1.1 * left * count / max(dt, 1e-6))))
     return {"value": count / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} seeded random strict pairs of the same matrix, "
                       f"sorting-kernel routine, {dt:.1f} s on {threads} threads "

@@ -1,9 +1,10 @@
 // Register-resident inversion count for the pair kernels (the Step 3 count of
 // Sec. 3.2, Algorithm 2, computed with a different merge schedule).
 //
-// A group of G lanes holds N = G*K keys, K per lane, lane-blocked (element
-// e = lane*K + r).  Keys are 16-bit dense ranks, packed two per VGPR: VGPR j
-// holds elements r = j (low half) and r = j + K/2 (high half).
+// A group of G lanes (8, 16 or 32 lanes of a wave, a whole wave, or a
+// 256-lane workgroup) holds N = G*K keys, K per lane, lane-blocked (element
+// e = lane*K + r).  Keys are 16-bit, twice a dense rank, packed two per VGPR:
+// VGPR j holds elements r = j (low half) and r = j + K/2 (high half).
 //
 // The sort is a bitonic network, level L merging sorted blocks of s = 2^L
 // into blocks of 2s.  Exactly as in Algorithm 2, the count of a level is, over
@@ -21,7 +22,7 @@
 // selecting min or max per lane, keys of a descending block are stored
 // complemented, so every comparator of every stage keeps the minimum at the
 // lower position; a complemented block's physical position q is ascending
-// position 2s-1-q, which flips the sign of its term (see level_count).
+// position 2s-1-q, which flips the sign of its term (see levels).
 //
 // Partners at distance d:  d < K/2 -> another VGPR of the same lane (one
 // v_pk_min_u16 + one v_pk_max_u16 for two comparators);  d = K/2 -> the two
@@ -61,8 +62,9 @@ struct Net {
   static constexpr int LOGG = ilog2(G);
   static constexpr int LOGN = LOGK + LOGG;
   static constexpr int N = K * G;
-  static_assert(K >= 2 && (K & (K - 1)) == 0, "K is a power of two");
-  static_assert(G == 64 || G == 256, "a wave or a 256-lane workgroup");
+  static_assert(K >= 2 && K <= 64 && (K & (K - 1)) == 0, "K is a power of two <= 64");
+  static_assert(G == 8 || G == 16 || G == 32 || G == 64 || G == 256,
+                "part of a wave, a wave or a 256-lane workgroup");
 
   // Bit b of element (lane, j, h).
   static __device__ __forceinline__ uint32_t ebit(int lane, int j, int h, int b) {
@@ -174,66 +176,76 @@ struct Net {
     if constexpr (k > 0) stages_down<L, k - 1>(v, lane, xbuf);
   }
 
-  // Re-tag for level L (tag = bit L of e, the half of the 2s block) and
-  // re-orient (complemented iff bit L+1 of e: a descending block).  The
-  // previous level stored key' ^ orient(bit L); working the cases through,
-  //   new = (old & 0xFFFE) ^ (bit L != bit L+1 ? 0xFFFF : 0)   per half,
-  // and level 0 starts from untagged ascending keys 2*rank.
+  // Tag-and-orientation constant of level L for VGPR j: tag = bit L of e (the
+  // half of the 2s block), complemented iff bit L+1 of e (a descending
+  // block).  The previous level stored key' ^ orient(bit L); working the
+  // cases through, the new key is (old & 0xFFFE) ^ c with
+  // c = (bit L != bit L+1 ? 0xFFFF : 0) per half, and level 0 starts from
+  // untagged ascending keys 2*rank with c = tag ^ orient.
   template <int L>
-  static __device__ __forceinline__ void retag(u16x2 (&v)[KV], int lane) {
-#pragma unroll
-    for (int j = 0; j < KV; ++j) {
-      uint32_t c;
-      if constexpr (L == 0) {
-        const uint32_t t0 = ebit(lane, j, 0, 0), t1 = ebit(lane, j, 1, 0);
-        c = (t0 | (t1 << 16)) ^ half_mask(ebit(lane, j, 0, 1), ebit(lane, j, 1, 1));
-      } else {
-        c = half_mask(ebit(lane, j, 0, L) ^ (L + 1 < LOGN ? ebit(lane, j, 0, L + 1) : 0u),
-                      ebit(lane, j, 1, L) ^ (L + 1 < LOGN ? ebit(lane, j, 1, L + 1) : 0u));
-      }
-      v[j] = vec((bits(v[j]) & 0xFFFEFFFEu) ^ c);
+  static __device__ __forceinline__ uint32_t tag_const(int lane, int j) {
+    if constexpr (L == 0) {
+      const uint32_t t0 = ebit(lane, j, 0, 0), t1 = ebit(lane, j, 1, 0);
+      return (t0 | (t1 << 16)) ^ half_mask(ebit(lane, j, 0, 1), ebit(lane, j, 1, 1));
+    } else {
+      return half_mask(ebit(lane, j, 0, L) ^ (L + 1 < LOGN ? ebit(lane, j, 0, L + 1) : 0u),
+                       ebit(lane, j, 1, L) ^ (L + 1 < LOGN ? ebit(lane, j, 1, L + 1) : 0u));
     }
   }
 
-  // Signed position sum of level L for this lane: sum over right-half
-  // elements of (+q if in a complemented block, -q otherwise), q being the
-  // physical position inside the 2s block.  Returned modulo 2^32.
+  // The count of level L is a sum over right-half elements of their
+  // ascending position in the merged block (see the top of this file).  With
+  // raw = the stored tag bit after the merge and q the physical position in
+  // the 2s block, a complemented block's elements have tag 1 - raw and
+  // ascending position 2s-1-q, and the level's term works out to
+  //   (sum of q over the lane's elements of complemented blocks) - sum raw*q,
+  // i.e. a per-lane constant minus one dot product of the raw tag bits.
+  // Blocks inside a lane: q depends on (j, half) only, so the constants and
+  // weights are compile-time.  Blocks spanning lanes: q = base + r (r = index
+  // in the lane, base the lane's offset in its block); the weights r + 4096
+  // give sum raw*r (< 4096) and the number of raw tags (above bit 12) in one
+  // accumulator.
+  static constexpr uint32_t in_lane_weight(int L, int j) {
+    const uint32_t m2s = (2u << L) - 1u;
+    return ((uint32_t)j & m2s) | (((uint32_t)(j + KV) & m2s) << 16);
+  }
+  static constexpr uint32_t in_lane_const() {
+    // sum over in-lane levels of the positions of complemented elements
+    uint32_t c = 0;
+    for (int L = 0; L + 1 < LOGK; ++L)
+      for (int r = 0; r < K; ++r)
+        if ((r >> (L + 1)) & 1) c += (uint32_t)r & ((2u << L) - 1u);
+    return c;
+  }
+
+  // Level L: its comparator stages, its count, and the re-tag for level L+1
+  // (one AND, one dot product and one XOR per VGPR).
   template <int L>
-  static __device__ __forceinline__ uint32_t level_count(const u16x2 (&v)[KV], int lane) {
-    uint32_t pos = 0, neg = 0;
-    if constexpr (L + 1 < LOGK) {
-      // block inside the lane: orientation and position are per (j, half)
+  static __device__ __forceinline__ void levels(u16x2 (&v)[KV], int lane, uint32_t* xbuf,
+                                                uint32_t& acc_in, uint32_t& total) {
+    stages_down<L, L>(v, lane, xbuf);
+    uint32_t acc = 0;
 #pragma unroll
-      for (int j = 0; j < KV; ++j) {
-        const uint32_t o0 = ebit(lane, j, 0, L + 1), o1 = ebit(lane, j, 1, L + 1);
-        const uint32_t t = (bits(v[j]) & 0x00010001u) ^ (o0 | (o1 << 16));
-        const uint32_t m2s = (2u << L) - 1u;
-        const uint32_t q0 = (uint32_t)j & m2s, q1 = ((uint32_t)(j + KV)) & m2s;
-        const uint32_t qd = (o0 ? q0 : 0u) | ((o1 ? q1 : 0u) << 16);
-        const uint32_t qa = (o0 ? 0u : q0) | ((o1 ? 0u : q1) << 16);
-        pos = __builtin_amdgcn_udot2(vec(t), vec(qd), pos, false);
-        neg = __builtin_amdgcn_udot2(vec(t), vec(qa), neg, false);
+    for (int j = 0; j < KV; ++j) {
+      const uint32_t t = bits(v[j]) & 0x00010001u;
+      if constexpr (L + 1 < LOGK) {
+        acc_in = __builtin_amdgcn_udot2(vec(t), vec(in_lane_weight(L, j)), acc_in, false);
+      } else {
+        const uint32_t w = ((uint32_t)j + 4096u) | (((uint32_t)(j + KV) + 4096u) << 16);
+        acc = __builtin_amdgcn_udot2(vec(t), vec(w), acc, false);
       }
-      return pos - neg;
-    } else {
-      // the lane lies inside one block: orientation and base are per lane
-      const bool desc = (L + 1 < LOGN) ? (((lane >> (L + 1 - LOGK)) & 1) != 0) : false;
-      const uint32_t om = desc ? 0x00010001u : 0u;
-      const uint32_t base = ((uint32_t)lane & ((1u << (L + 1 - LOGK)) - 1u)) << LOGK;
-      uint32_t cnt = 0, dsum = 0;
-#pragma unroll
-      for (int j = 0; j < KV; ++j) {
-        const uint32_t t = (bits(v[j]) & 0x00010001u) ^ om;
-        const uint32_t qj = (uint32_t)j | ((uint32_t)(j + KV) << 16);
-        dsum = __builtin_amdgcn_udot2(vec(t), vec(qj), dsum, false);
-        cnt += t;
-      }
-      const uint32_t s = dsum + base * ((cnt & 0xFFFFu) + (cnt >> 16));
-      // +s for a complemented block, -s otherwise: (s ^ m) - m with m all ones
-      // negates, computed without a scalar condition mask
-      const uint32_t m = desc ? 0u : 0xFFFFFFFFu;
-      return (s ^ m) - m;
+      if constexpr (L + 1 < LOGN) v[j] = vec(bits(v[j]) ^ t ^ tag_const<L + 1>(lane, j));
     }
+    if constexpr (L + 1 >= LOGK) {
+      // the lane lies inside one block of 2s: its offset and orientation
+      const uint32_t base = ((uint32_t)lane & ((1u << (L + 1 - LOGK)) - 1u)) << LOGK;
+      const uint32_t raw = (acc & 4095u) + base * (acc >> 12);
+      const uint32_t desc =
+          (L + 1 < LOGN) ? (uint32_t)(lane >> (L + 1 - LOGK)) & 1u : 0u;
+      const uint32_t all = (uint32_t)K * base + (uint32_t)(K * (K - 1) / 2);
+      total += (all & (0u - desc)) - raw;
+    }
+    if constexpr (L + 1 < LOGN) levels<L + 1>(v, lane, xbuf, acc_in, total);
   }
 
   // Constant part of all levels: a level with nb >= 2 blocks of 2s adds
@@ -249,26 +261,17 @@ struct Net {
     return (uint32_t)c;
   }
 
-  template <int L>
-  static __device__ __forceinline__ uint32_t levels(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
-    retag<L>(v, lane);
-    stages_down<L, L>(v, lane, xbuf);
-    uint32_t c = level_count<L>(v, lane);
-    if constexpr (L + 1 < LOGN) c += levels<L + 1>(v, lane, xbuf);
-    return c;
-  }
-
-  // keys: 16-bit ranks (padding = 0x7FFF).  Returns this lane's share of the
-  // group's strict inversion count (the constant part is added by lane 0).
-  static __device__ __forceinline__ uint32_t count(const uint32_t (&key)[K], int lane,
-                                                   uint32_t* xbuf) {
-    u16x2 v[KV];
+  // v: packed keys 2*rank (padding 0xFFFE), sorted in place.  Returns this
+  // lane's share of the group's strict inversion count (the constant part is
+  // added by lane 0 of the group), modulo 2^32.
+  static __device__ __forceinline__ uint32_t count(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
 #pragma unroll
-    for (int j = 0; j < KV; ++j)
-      v[j] = vec(((key[j] & 0x7FFFu) << 1) | ((key[j + KV] & 0x7FFFu) << 17));
-    uint32_t c = levels<0>(v, lane, xbuf);
-    if (lane == 0) c += constant_part();
-    return c;
+    for (int j = 0; j < KV; ++j) v[j] = vec(bits(v[j]) ^ tag_const<0>(lane, j));
+    uint32_t acc_in = 0, total = in_lane_const();
+    levels<0>(v, lane, xbuf, acc_in, total);
+    total -= acc_in;
+    if (lane == 0) total += constant_part();
+    return total;
   }
 };
 

@@ -79,22 +79,50 @@ struct PairOut {
   double* tau_a;
 };
 
-// Per-pair schemes.  A "group" of G lanes (one wave, or a whole 256-lane
-// block) sorts one pair's n <= G*K keys, K keys per lane.
+// Per-pair schemes.  A "group" of G lanes (8, 16 or 32 lanes of a wave, a
+// whole wave, or a 256-lane block) sorts one pair's n <= G*K keys, K keys per
+// lane.  Smaller groups keep more of the network inside each lane's
+// registers; the list below is (enum, K, G) of every scheme.
+#define KTAU_FOR_EACH_SCHEME(X) \
+  X(kWaveK2, 2, 64)             \
+  X(kWaveK4, 4, 64)             \
+  X(kWaveK8, 8, 64)             \
+  X(kWaveK16, 16, 64)           \
+  X(kBlockK4, 4, 256)           \
+  X(kBlockK8, 8, 256)           \
+  X(kBlockK16, 16, 256)         \
+  X(kSub8K16, 16, 8)            \
+  X(kSub16K16, 16, 16)          \
+  X(kSub16K32, 32, 16)          \
+  X(kSub16K64, 64, 16)          \
+  X(kSub32K32, 32, 32)          \
+  X(kSub32K64, 64, 32)          \
+  X(kWaveK32, 32, 64)           \
+  X(kWaveK64, 64, 64)           \
+  X(kSub8K32, 32, 8)            \
+  X(kSub8K64, 64, 8)
+
 enum Scheme : int32_t {
-  kWaveK2 = 0,
-  kWaveK4 = 1,
-  kWaveK8 = 2,
-  kWaveK16 = 3,
-  kBlockK4 = 4,
-  kBlockK8 = 5,
-  kBlockK16 = 6,
-  kNumSchemes = 7
+#define KTAU_ENUM(S, K, G) S,
+  KTAU_FOR_EACH_SCHEME(KTAU_ENUM)
+#undef KTAU_ENUM
+  kNumSchemes
 };
 
-inline int scheme_lanes(int s) { return s <= kWaveK16 ? 64 : 256; }
+inline int scheme_lanes(int s) {
+  static const int g[] = {
+#define KTAU_G(S, K, G) G,
+      KTAU_FOR_EACH_SCHEME(KTAU_G)
+#undef KTAU_G
+  };
+  return g[s];
+}
 inline int scheme_k(int s) {
-  static const int k[] = {2, 4, 8, 16, 4, 8, 16};
+  static const int k[] = {
+#define KTAU_K(S, K, G) K,
+      KTAU_FOR_EACH_SCHEME(KTAU_K)
+#undef KTAU_K
+  };
   return k[s];
 }
 inline int64_t scheme_capacity(int s) { return (int64_t)scheme_lanes(s) * scheme_k(s); }

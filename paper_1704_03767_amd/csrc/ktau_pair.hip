@@ -180,16 +180,15 @@ constexpr int kCompLdsWords = CompLds<16, 256>::kWords > 4 * CompLds<16, 64>::kW
                                   ? CompLds<16, 256>::kWords
                                   : 4 * CompLds<16, 64>::kWords;
 
+// The composite pass runs on whole waves or 256-lane blocks, chosen by n
+// alone (it is rare; the fast path's scheme does not matter to it).
 __device__ void composite_dispatch(const MatDesc& d, uint32_t* lds, uint32_t* red) {
-  switch (d.scheme) {
-    case kWaveK2: composite_matrix<2, 64>(d, lds, red); break;
-    case kWaveK4: composite_matrix<4, 64>(d, lds, red); break;
-    case kWaveK8: composite_matrix<8, 64>(d, lds, red); break;
-    case kWaveK16: composite_matrix<16, 64>(d, lds, red); break;
-    case kBlockK4: composite_matrix<4, 256>(d, lds, red); break;
-    case kBlockK8: composite_matrix<8, 256>(d, lds, red); break;
-    default: composite_matrix<16, 256>(d, lds, red); break;
-  }
+  if (d.n <= 128) composite_matrix<2, 64>(d, lds, red);
+  else if (d.n <= 256) composite_matrix<4, 64>(d, lds, red);
+  else if (d.n <= 512) composite_matrix<8, 64>(d, lds, red);
+  else if (d.n <= 1024) composite_matrix<16, 64>(d, lds, red);
+  else if (d.n <= 2048) composite_matrix<8, 256>(d, lds, red);
+  else composite_matrix<16, 256>(d, lds, red);
 }
 
 __global__ void __launch_bounds__(kBlock) composite_plain_kernel(MatDesc d) {
@@ -246,18 +245,23 @@ hipError_t launch_jobs_t(const MatDesc& d, hipStream_t s) {
 }  // namespace
 
 const char* scheme_name(int s) {
-  static const char* names[] = {"wave_k2", "wave_k4", "wave_k8", "wave_k16",
-                                "block_k4", "block_k8", "block_k16"};
+  static const char* names[] = {"wave_k2",   "wave_k4",   "wave_k8",   "wave_k16",  "block_k4",
+                                "block_k8",  "block_k16", "sub8_k16",  "sub16_k16", "sub16_k32",
+                                "sub16_k64", "sub32_k32", "sub32_k64", "wave_k32",  "wave_k64",
+                                "sub8_k32",  "sub8_k64"};
+  static_assert(sizeof(names) / sizeof(names[0]) == kNumSchemes, "one name per scheme");
   return (s >= 0 && s < kNumSchemes) ? names[s] : "invalid";
 }
 
+// Fastest scheme per capacity class on MI355X (measured: the smallest group
+// whose network fits, within the LDS each in-flight pair needs).
 int default_scheme(int64_t n) {
-  if (n <= 128) return kWaveK2;
-  if (n <= 256) return kWaveK4;
-  if (n <= 512) return kWaveK8;
-  if (n <= 1024) return kWaveK16;
-  if (n <= 2048) return kBlockK8;
-  return kBlockK16;
+  if (n <= 128) return kSub8K16;
+  if (n <= 256) return kSub8K32;
+  if (n <= 512) return kSub16K32;
+  if (n <= 1024) return kSub32K32;
+  if (n <= 2048) return kWaveK32;
+  return kWaveK64;
 }
 
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
@@ -265,13 +269,7 @@ hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
 #define KTAU_CASE(S, K, G) \
   case S: e = tiles ? launch_tiles_t<K, G>(d, s) : launch_jobs_t<K, G>(d, s); break;
   switch (d.scheme) {
-    KTAU_CASE(kWaveK2, 2, 64)
-    KTAU_CASE(kWaveK4, 4, 64)
-    KTAU_CASE(kWaveK8, 8, 64)
-    KTAU_CASE(kWaveK16, 16, 64)
-    KTAU_CASE(kBlockK4, 4, 256)
-    KTAU_CASE(kBlockK8, 8, 256)
-    KTAU_CASE(kBlockK16, 16, 256)
+    KTAU_FOR_EACH_SCHEME(KTAU_CASE)
     default: return hipErrorInvalidValue;
   }
 #undef KTAU_CASE
@@ -308,13 +306,10 @@ hipError_t launch_pairs_persistent(int scheme, const MatDesc* d, int64_t count, 
                                    const int64_t* prefix, int64_t* counter, const int32_t* status,
                                    hipStream_t s) {
   switch (scheme) {
-    case kWaveK2: return persistent_t<2, 64>(d, count, total, prefix, counter, status, s);
-    case kWaveK4: return persistent_t<4, 64>(d, count, total, prefix, counter, status, s);
-    case kWaveK8: return persistent_t<8, 64>(d, count, total, prefix, counter, status, s);
-    case kWaveK16: return persistent_t<16, 64>(d, count, total, prefix, counter, status, s);
-    case kBlockK4: return persistent_t<4, 256>(d, count, total, prefix, counter, status, s);
-    case kBlockK8: return persistent_t<8, 256>(d, count, total, prefix, counter, status, s);
-    case kBlockK16: return persistent_t<16, 256>(d, count, total, prefix, counter, status, s);
+#define KTAU_CASE(S, K, G) \
+  case S: return persistent_t<K, G>(d, count, total, prefix, counter, status, s);
+    KTAU_FOR_EACH_SCHEME(KTAU_CASE)
+#undef KTAU_CASE
     default: return hipErrorInvalidValue;
   }
 }

@@ -20,9 +20,9 @@ constexpr int64_t kMaxPairGrid = 8192;
 
 template <int G>
 __device__ __forceinline__ void group_sync() {
-  if constexpr (G == 64) {
-    // one wave: LDS operations of a wave complete in order; this only stops
-    // the compiler from moving LDS accesses across the point
+  if constexpr (G <= 64) {
+    // inside one wave: LDS operations of a wave complete in order; this only
+    // stops the compiler from moving LDS accesses across the point
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -37,21 +37,27 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// Sum over the group; every lane gets the total.
+// Sum over the group; every lane of the group gets the total.
 template <int G>
 __device__ __forceinline__ uint32_t group_sum(uint32_t v, uint32_t* red) {
-  v = wave_sum(v);
-  if constexpr (G == 64) {
+  if constexpr (G < 64) {
+#pragma unroll
+    for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
   } else {
-    const int wave = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[wave] = v;
-    __syncthreads();
-    uint32_t t = 0;
+    v = wave_sum(v);
+    if constexpr (G == 64) {
+      return v;
+    } else {
+      const int wave = threadIdx.x >> 6;
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) red[wave] = v;
+      __syncthreads();
+      uint32_t t = 0;
 #pragma unroll
-    for (int w = 0; w < G / 64; ++w) t += red[w];
-    return t;
+      for (int w = 0; w < G / 64; ++w) t += red[w];
+      return t;
+    }
   }
 }
 
@@ -87,6 +93,41 @@ __device__ __forceinline__ void store_u16(uint16_t* p, const uint16_t (&in)[K]) 
 #pragma unroll
   for (int i = 0; i < K / 2; ++i)
     ((uint32_t*)p)[i] = (uint32_t)in[2 * i] | ((uint32_t)in[2 * i + 1] << 16);
+}
+
+// K consecutive uint16 as K/2 packed words (element 2i low, 2i+1 high), from
+// a 2K-byte aligned address.
+template <int K>
+__device__ __forceinline__ void load_words(const uint16_t* p, uint32_t (&w)[K / 2]) {
+  if constexpr (K == 2) {
+    w[0] = *(const uint32_t*)p;
+  } else if constexpr (K == 4) {
+    const uint2 a = *(const uint2*)p;
+    w[0] = a.x;
+    w[1] = a.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < K / 8; ++i) {
+      const uint4 a = ((const uint4*)p)[i];
+      w[4 * i] = a.x;
+      w[4 * i + 1] = a.y;
+      w[4 * i + 2] = a.z;
+      w[4 * i + 3] = a.w;
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void store_words(uint16_t* p, const uint32_t (&w)[K / 2]) {
+  if constexpr (K == 2) {
+    *(uint32_t*)p = w[0];
+  } else if constexpr (K == 4) {
+    *(uint2*)p = make_uint2(w[0], w[1]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < K / 8; ++i)
+      ((uint4*)p)[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+  }
 }
 
 // Step 5 and Eq. 1/3: store the counts and tau of job slot `slot`.
@@ -160,6 +201,8 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
                                           uint32_t* red, int lane, uint32_t& nd, uint32_t& n3) {
   using FL = FastLds<K, G>;
   using Net = bitonic::Net<K, G>;
+  using bitonic::u16x2;
+  constexpr int KV = K / 2;
   const int64_t n1y = ry.n1[y], n1x = rx.n1[x];
   if (n1y > budget && n1x > budget) return false;
   // u: the row with fewer ties; both views share the row stride
@@ -170,32 +213,58 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
   const int64_t n1u = swap ? n1x : n1y;
   const int64_t ld = ry.ld;
   const int k0 = lane * K;
-  const bool in_row = k0 + K <= ld;              // vector loads stay inside the row
+  // vector loads stay inside the row (ld is a multiple of 64, so a lane is
+  // either wholly inside or wholly past n)
+  const bool in_row = k0 + K <= ld;
   uint16_t* row = (uint16_t*)lds;
   uint32_t* xbuf = lds + FL::kRowWords;
   // stage v's rank row in LDS
-  {
-    uint16_t r[K];
-    if (in_row) {
-      load_u16<K>(rv_v.rank + v * ld + k0, r);
-      store_u16<K>(row + k0, r);
-    }
+  if (in_row) {
+    uint32_t w[KV];
+    load_words<K>(rv_v.rank + v * ld + k0, w);
+    store_words<K>(row + k0, w);
   }
-  uint16_t p[K];
-  if (in_row) load_u16<K>(ru_v.perm + u * ld + k0, p);
-  group_sync<G>();
-  uint32_t key[K];
+  uint32_t pw[KV];
+  if (in_row) {
+    load_words<K>(ru_v.perm + u * ld + k0, pw);
+  } else {
 #pragma unroll
-  for (int r = 0; r < K; ++r) key[r] = (k0 + r < n) ? (uint32_t)row[p[r]] : 0x7FFFu;
+    for (int i = 0; i < KV; ++i) pw[i] = 0;
+  }
+  group_sync<G>();
+  // v'[k] = rank_v[perm_u[k]], packed: VGPR j holds k0 + j and k0 + j + KV;
+  // keys are 2 v' (the network's tag goes in bit 0).  Row tails past n hold
+  // perm[k] = k and rank 0x7FFF, so they gather the padding key 0xFFFE; lanes
+  // wholly past the row get it directly.
+  u16x2 key[KV];
+#pragma unroll
+  for (int j = 0; j < KV; ++j) {
+    const uint32_t a = j % 2 ? pw[j / 2] >> 16 : pw[j / 2] & 0xFFFFu;
+    const uint32_t b = (j + KV) % 2 ? pw[(j + KV) / 2] >> 16 : pw[(j + KV) / 2] & 0xFFFFu;
+    u16x2 t;
+    t.x = row[a];
+    t.y = row[b];
+    key[j] = in_row ? (u16x2)(t << (unsigned short)1) : bitonic::vec(0xFFFEFFFEu);
+  }
   uint32_t xin = 0, tie = 0;
   if (n1u != 0) {
-    // v' in u order replaces the rank row once every lane has gathered
+    // 2 v' in u order replaces the rank row once every lane has gathered
     group_sync<G>();
-    {
-      uint16_t kv[K];
+    if (in_row) {
+      uint32_t w[KV];
+      if constexpr (KV == 1) {
+        w[0] = bitonic::bits(key[0]);
+      } else {
 #pragma unroll
-      for (int r = 0; r < K; ++r) kv[r] = (uint16_t)key[r];
-      if (in_row) store_u16<K>(row + k0, kv);
+        for (int i = 0; i < KV / 2; ++i) {
+          // positions k0 + 2i, 2i + 1 (low halves), k0 + KV + 2i, 2i + 1 (high)
+          w[i] = __builtin_amdgcn_perm(bitonic::bits(key[2 * i + 1]), bitonic::bits(key[2 * i]),
+                                       0x05040100u);
+          w[KV / 2 + i] = __builtin_amdgcn_perm(bitonic::bits(key[2 * i + 1]),
+                                                bitonic::bits(key[2 * i]), 0x07060302u);
+        }
+      }
+      store_words<K>(row + k0, w);
     }
     group_sync<G>();
     // positions up to the end of u's last tie run, spread over lanes with
@@ -213,14 +282,11 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
       }
     }
   }
-  const uint32_t inv = group_sum<G>(Net::count(key, lane, xbuf), red);
-  if (n1u != 0) {
-    nd = inv - group_sum<G>(xin, red);
-    n3 = group_sum<G>(tie, red);
-  } else {
-    nd = inv;
-    n3 = 0;
-  }
+  // n_d = inversions - inversions inside u runs, summed in one reduction
+  // (exact modulo 2^32)
+  const uint32_t share = Net::count(key, lane, xbuf) - xin;
+  nd = group_sum<G>(share, red);
+  n3 = n1u != 0 ? group_sum<G>(tie, red) : 0u;
   return true;
 }
 

@@ -155,18 +155,20 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
       ties += (unsigned long long)(k - st);
       if (k > st) last_tied = k + 1;
     } else if (k < ld) {
-      if (prow) prow[k] = 0;
+      if (prow) prow[k] = (uint16_t)k;
       if (srow) srow[k] = (uint16_t)k;
     }
   }
   // Padding of rows longer than the sort width (ld > npow2 never happens for
   // the workspace layout, but callers may pass a wider ld).
   for (int k = npow2 + tid; k < ld; k += kThreads) {
-    if (prow) prow[k] = 0;
+    if (prow) prow[k] = (uint16_t)k;
     if (srow) srow[k] = (uint16_t)k;
   }
+  // Tail positions n..ld-1 map to themselves and rank 0x7FFF, above every
+  // real rank, so the pair kernels gather padding keys without a bounds test.
   if (rrow)
-    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = 0;
+    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)0x7FFF;
   atomicAdd(&s_n1, ties);
   atomicMax(&s_tie_end, last_tied);
   __syncthreads();

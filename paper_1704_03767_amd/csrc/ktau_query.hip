@@ -172,9 +172,20 @@ hipError_t query_pairs_t(const QueryDesc& qd, hipStream_t s) {
   if (grid > kMaxPairGrid) grid = kMaxPairGrid;
   if (grid < 1) return hipSuccess;
   hipLaunchKernelGGL((query_pairs_kernel<K, G>), dim3((unsigned)grid), dim3(kBlock), 0, s, qd);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((query_composite_kernel<K, G>), dim3(256), dim3(kBlock), 0, s, qd);
+  return hipGetLastError();
+}
+
+// Heavy x heavy pairs, on whole waves or 256-lane blocks chosen by n.
+hipError_t query_composite(const QueryDesc& qd, hipStream_t s) {
+#define KTAU_COMP(K, G) \
+  hipLaunchKernelGGL((query_composite_kernel<K, G>), dim3(256), dim3(kBlock), 0, s, qd)
+  if (qd.n <= 128) KTAU_COMP(2, 64);
+  else if (qd.n <= 256) KTAU_COMP(4, 64);
+  else if (qd.n <= 512) KTAU_COMP(8, 64);
+  else if (qd.n <= 1024) KTAU_COMP(16, 64);
+  else if (qd.n <= 2048) KTAU_COMP(8, 256);
+  else KTAU_COMP(16, 256);
+#undef KTAU_COMP
   return hipGetLastError();
 }
 
@@ -244,14 +255,13 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
   qd.db_heavy_count = db.heavy_count;
   hipError_t e;
   switch (db.scheme) {
-    case kWaveK2: e = query_pairs_t<2, 64>(qd, s); break;
-    case kWaveK4: e = query_pairs_t<4, 64>(qd, s); break;
-    case kWaveK8: e = query_pairs_t<8, 64>(qd, s); break;
-    case kWaveK16: e = query_pairs_t<16, 64>(qd, s); break;
-    case kBlockK4: e = query_pairs_t<4, 256>(qd, s); break;
-    case kBlockK8: e = query_pairs_t<8, 256>(qd, s); break;
-    default: e = query_pairs_t<16, 256>(qd, s); break;
+#define KTAU_CASE(S, K, G) \
+  case S: e = query_pairs_t<K, G>(qd, s); break;
+    KTAU_FOR_EACH_SCHEME(KTAU_CASE)
+#undef KTAU_CASE
+    default: e = hipErrorInvalidValue; break;
   }
+  if (e == hipSuccess) e = query_composite(qd, s);
   if (e != hipSuccess) return KTAU_EDEVICE;
 
   // top-k rounds: tau -> ia -> ib -> ia ...
@@ -296,7 +306,10 @@ int ktau_db_create(const float* X, int64_t m, int64_t n, void* stream, ktau_db**
   ktau_db* db = new ktau_db();
   db->v.m = m;
   db->v.n = n;
-  db->v.scheme = default_scheme(n);
+  // KTAU_FORCE_SCHEME (tests, tuning) picks another scheme that holds n
+  db->v.scheme = env_int("KTAU_FORCE_SCHEME", default_scheme(n));
+  if (db->v.scheme < 0 || db->v.scheme >= kNumSchemes || scheme_capacity(db->v.scheme) < n)
+    db->v.scheme = default_scheme(n);
   const WsLayout L = ws_layout(m, n);
   if (hipMalloc(&db->ws, L.total) != hipSuccess) {
     delete db;

@@ -50,7 +50,7 @@ def test_batch_forced_schemes():
     mats = _small_batch(10, 43)
     dev = [torch.from_numpy(X).cuda() for X in mats]
     want = [oracle.allpairs(X, "gse") for X in mats]
-    for scheme in ("block_k16", "block_k8"):
+    for scheme in ("block_k16", "block_k8", "wave_k64", "sub16_k64", "sub8_k16"):
         small = [i for i, X in enumerate(mats) if X.shape[1] <= K.ktau_scheme_capacity(
             K.scheme_id(scheme))]
         b = K.KtauBatch([dev[i] for i in small], force_scheme=scheme, force_q=3)

@@ -15,6 +15,7 @@ from paper_1704_03767_amd import synth
 
 pytestmark = pytest.mark.gpu
 TAU_TOL = 1e-15
+ALL_SCHEMES = list(range(len(K.ktau_scheme_names())))
 
 
 def _np(d):
@@ -89,7 +90,7 @@ def test_prepass_matches_oracle(shape_seed):
 # ------------------------------------------------------------ small workload
 
 
-@pytest.mark.parametrize("scheme", list(range(7)))
+@pytest.mark.parametrize("scheme", ALL_SCHEMES)
 def test_small_workload_every_scheme(scheme):
     X = synth.config_matrix(1)                              # 64 x 128, ties from rounding
     _check_full(X, scheme=scheme)
@@ -144,10 +145,10 @@ def test_edge_sample_counts(n):
         assert np.isnan(got["tau_b"][K.ktau_pair_to_job(m, 0, x)])
 
 
-@pytest.mark.parametrize("n", [100, 700, 1500, 3000])
+@pytest.mark.parametrize("n", [100, 700, 1024, 1500, 3000, 4096])
 def test_block_schemes_on_edges(n):
     X = _edge_matrix(9, n, 7 + n)
-    for scheme in range(7):
+    for scheme in ALL_SCHEMES:
         if K.ktau_scheme_capacity(scheme) >= n:
             _check_full(X, scheme=scheme)
 
@@ -171,7 +172,9 @@ def test_heavy_tie_paths():
         rows.append(np.where(rng.random(n) < 0.9, 0.0, rng.standard_normal(n)).astype(np.float32))
         rows.append(np.where(rng.random(n) < 0.05, 0.0, rng.standard_normal(n)).astype(np.float32))
         X = np.stack(rows)
-        _check_full(X)
+        for scheme in ALL_SCHEMES:
+            if K.ktau_scheme_capacity(scheme) >= n:
+                _check_full(X, scheme=scheme)
 
 
 # ------------------------------------------------------------ job sub-ranges
@@ -187,7 +190,7 @@ def test_ranges_equal_full_slices():
         part = _np(K.ktau_allpairs_range(Xd, a, b))
         for k in ("nc", "nd", "n3", "tau_b"):
             assert np.array_equal(part[k], full[k][a:b], equal_nan=True), (a, b, k)
-    for scheme in (0, 4):
+    for scheme in ALL_SCHEMES:
         part = _np(K.ktau_allpairs_range(Xd, 7, 1500, scheme=scheme))
         for k in ("nc", "nd", "n3", "tau_b"):
             assert np.array_equal(part[k], full[k][7:1500], equal_nan=True)

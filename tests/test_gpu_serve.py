@@ -55,6 +55,22 @@ def test_query_matches_oracle(k):
     kdb.close()
 
 
+def test_query_every_scheme(monkeypatch):
+    db = _db(m=500, n=300, seed=56)
+    Q = _queries(db, 3, 57)
+    Q[0, :40] = 0.0                                          # ties on the query side
+    want = oracle.query_topk(db.X, Q, 20)
+    for s, name in enumerate(K.ktau_scheme_names()):
+        if K.ktau_scheme_capacity(s) < db.X.shape[1]:
+            continue
+        monkeypatch.setenv("KTAU_FORCE_SCHEME", str(s))
+        kdb = S.KtauDb(torch.from_numpy(db.X).cuda())
+        got = {a: b.cpu().numpy()
+               for a, b in S.ktau_query(kdb, torch.from_numpy(Q).cuda(), 20).items()}
+        _check_topk(got, want)
+        kdb.close()
+
+
 def test_query_pads_when_k_exceeds_rows():
     db = _db(m=40, n=300, seed=53)
     Q = _queries(db, 3, 54)
