@@ -26,8 +26,10 @@ WsLayout ws_layout(int64_t m, int64_t n) {
   off = round_up(off + rowbytes, (int64_t)kAlign);
   L.n1 = (size_t)off;
   off = round_up(off + m * (int64_t)sizeof(int64_t), (int64_t)kAlign);
-  L.tie_end = (size_t)off;
+  L.nruns = (size_t)off;
   off = round_up(off + m * (int64_t)sizeof(int32_t), (int64_t)kAlign);
+  L.runs = (size_t)off;
+  off = round_up(off + m * (L.ld / 2) * (int64_t)sizeof(uint64_t), (int64_t)kAlign);
   L.heavy = (size_t)off;
   off = round_up(off + m * (int64_t)sizeof(int32_t), (int64_t)kAlign);
   L.total = (size_t)off;
@@ -56,7 +58,8 @@ MatDesc matdesc(void* ws, int64_t m, int64_t n, const ktau_pair_out& out, int sc
   d.rv.rank = (const uint16_t*)(base + L.rank);
   d.rv.rstart = (const uint16_t*)(base + L.rstart);
   d.rv.n1 = (const int64_t*)(base + L.n1);
-  d.rv.tie_end = (const int32_t*)(base + L.tie_end);
+  d.rv.nruns = (const int32_t*)(base + L.nruns);
+  d.rv.runs = (const uint64_t*)(base + L.runs);
   d.rv.ld = L.ld;
   d.out = PairOut{out.nc, out.nd, out.n3, out.tau_b, out.tau_a};
   d.status = status ? status : (const int32_t*)base;
@@ -80,7 +83,8 @@ int prepass_ws(const float* X, int64_t m, int64_t n, void* ws, int64_t* n1_out, 
   char* base = (char*)ws;
   if (launch_prepass(X, m, n, (uint16_t*)(base + L.perm), (uint16_t*)(base + L.rank),
                      (uint16_t*)(base + L.rstart), L.ld, (int64_t*)(base + L.n1), n1_out,
-                     (int32_t*)(base + L.tie_end), status ? status : (int32_t*)base,
+                     (int32_t*)(base + L.nruns), (uint64_t*)(base + L.runs),
+                     status ? status : (int32_t*)base,
                      s) != hipSuccess)
     return KTAU_EDEVICE;
   return KTAU_OK;
@@ -164,7 +168,7 @@ int ktau_rank(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* ra
   if (!X || !status || m < 1 || n < 1 || m > (int64_t)0x7fffffff) return KTAU_EINVAL;
   if (n > KTAU_MAX_N) return KTAU_ERANGE;
   const hipError_t e = launch_prepass(X, m, n, perm, rank, rstart, n, nullptr, n1, nullptr,
-                                      status, (hipStream_t)stream);
+                                      nullptr, status, (hipStream_t)stream);
   return e == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
 }
 

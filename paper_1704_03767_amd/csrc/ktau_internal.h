@@ -67,8 +67,11 @@ struct RankView {
   const uint16_t* rank;     // [rows][ld] sample -> dense rank
   const uint16_t* rstart;   // [rows][ld] sorted position -> first position of its tie run
   const int64_t* n1;        // [rows]
-  const int32_t* tie_end;   // [rows] 1 + last sorted position inside a tie run (0: no ties)
-  int64_t ld;               // row stride in elements
+  const int32_t* nruns;     // [rows] number of tie runs of length >= 2
+  // [rows][ld/2] tie runs of length >= 2 in sorted order: bits 0-15 start,
+  // 16-31 length, 32-63 number of within-run pairs of the earlier runs
+  const uint64_t* runs;
+  int64_t ld;               // row stride in elements (runs: ld/2 per row)
 };
 
 struct PairOut {
@@ -162,7 +165,7 @@ struct MatDesc {
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* tie_end, int32_t* status, hipStream_t s);
+                          int32_t* nruns, uint64_t* runs, int32_t* status, hipStream_t s);
 
 // Rank pre-pass of every row of every matrix of a descriptor table.
 hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t total_rows,
@@ -184,7 +187,7 @@ hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, hipS
 // ---- host helpers shared by the API units (ktau_api.hip)
 
 struct WsLayout {
-  size_t perm, rank, rstart, n1, tie_end, heavy, total;
+  size_t perm, rank, rstart, n1, nruns, runs, heavy, total;
   int64_t ld;
 };
 WsLayout ws_layout(int64_t m, int64_t n);

@@ -267,18 +267,60 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
       store_words<K>(row + k0, w);
     }
     group_sync<G>();
-    // positions up to the end of u's last tie run, spread over lanes with
-    // stride G so that one run is shared by many lanes; each is compared
-    // with the earlier positions of its run
-    const uint16_t* ru = ru_v.rstart + u * ld;
-    const int end = ru_v.tie_end[u];
-    for (int k = lane; k < end; k += G) {
-      const int s = ru[k];
-      const uint32_t me = row[k];
-      for (int j = s; j < k; ++j) {
-        const uint32_t o = row[j];
-        xin += o > me ? 1u : 0u;
-        tie += o == me ? 1u : 0u;
+    // The n1_u pairs of positions inside one tie run of u (Step 2), split
+    // evenly among the lanes: lane l takes pairs [l c, (l+1) c) of the
+    // sequence that numbers a run's pairs by the later position b, then the
+    // earlier a (index b(b-1)/2 + a), run after run.  Each pair adds to X
+    // when the earlier v' is larger and to n3 when they are equal.
+    const uint64_t* rl = ru_v.runs + u * (ld / 2);
+    const uint32_t total = (uint32_t)n1u;
+    const uint32_t per = (total + G - 1) / G;
+    uint32_t p = (uint32_t)lane * per;
+    const uint32_t cnt = p < total ? (total - p < per ? total - p : per) : 0u;
+    if (cnt > 0) {
+      // the run holding pair p: the last run whose pair prefix is <= p
+      int lo = 0, hi = ru_v.nruns[u] - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)(rl[mid] >> 32) <= p) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint64_t e = rl[lo];
+      const uint32_t start = (uint32_t)e & 0xFFFFu, len = (uint32_t)(e >> 16) & 0xFFFFu;
+      const uint32_t qi = p - (uint32_t)(e >> 32);
+      // b(b-1)/2 <= qi < b(b+1)/2 (a float estimate, then exact integer fix-up)
+      uint32_t b = (uint32_t)((1.0f + __fsqrt_rn(8.0f * (float)qi + 1.0f)) * 0.5f);
+      while (b * (b - 1) / 2 > qi) --b;
+      while (b * (b + 1) / 2 <= qi) ++b;
+      const uint32_t a = qi - b * (b - 1) / 2;
+      // byte offsets in the LDS row: earlier position, later position, run
+      // start and end; the next earlier value is loaded one step ahead
+      const char* rb = (const char*)row;
+      uint32_t oa = 2 * (start + a), ob = 2 * (start + b);
+      uint32_t os = 2 * start, oe = 2 * (start + len);
+      uint32_t me = *(const uint16_t*)(rb + ob);
+      uint32_t o = *(const uint16_t*)(rb + oa);
+      for (uint32_t left = cnt; left > 0; --left) {
+        const uint32_t cur = o;
+        oa += 2;
+        o = *(const uint16_t*)(rb + oa);   // oa <= ob: inside the row
+        xin += cur > me ? 1u : 0u;
+        tie += cur == me ? 1u : 0u;
+        if (oa == ob) {
+          ob += 2;
+          if (ob == oe) {
+            // next run; it exists whenever pairs remain
+            if (left > 1) {
+              const uint64_t e2 = rl[++lo];
+              os = 2 * ((uint32_t)e2 & 0xFFFFu);
+              oe = os + 2 * ((uint32_t)(e2 >> 16) & 0xFFFFu);
+            }
+            ob = os + 2;
+          }
+          oa = os;
+          me = *(const uint16_t*)(rb + ob);
+          o = *(const uint16_t*)(rb + oa);
+        }
       }
     }
   }

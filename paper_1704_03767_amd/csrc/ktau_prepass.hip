@@ -2,7 +2,9 @@
 // half of the sorting kernel's Steps 1, 2 and 4 (Sec. 3.2) is done here once
 // per row instead of once per pair: the ascending order of the row (ties by
 // sample index), its dense ranks, the start of every tie run, and the tie term
-// n1 = sum t(t-1)/2.
+// n1 = sum t(t-1)/2; and the list of its tie runs with the number of
+// within-run pairs before each, so that the pair kernels can share a pair's
+// in-run comparisons evenly among lanes.
 //
 // One 256-thread workgroup per row.  The row's (value key, sample) pairs are
 // bitonic-sorted in LDS as 64-bit words (order-preserving 32-bit key << 16 |
@@ -72,11 +74,10 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
                             uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                             uint16_t* __restrict__ rstart, int64_t ld,
                             int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
-                            int32_t* __restrict__ tie_end, int32_t* __restrict__ status,
-                            uint64_t* s_keys) {
+                            int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
+                            int32_t* __restrict__ status, uint64_t* s_keys) {
   __shared__ int s_scan[kThreads / 64];
   __shared__ unsigned long long s_n1;
-  __shared__ int s_tie_end;
   const float* x = X + row * (int64_t)n;
   const int tid = threadIdx.x;
 
@@ -91,10 +92,7 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
     }
     s_keys[i] = w;
   }
-  if (tid == 0) {
-    s_n1 = 0;
-    s_tie_end = 0;
-  }
+  if (tid == 0) s_n1 = 0;
   if (__syncthreads_or(any_nan)) {
     if (tid == 0) atomicExch(status, KTAU_ENAN);
     return;
@@ -139,7 +137,6 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
   uint16_t* srow = rstart ? rstart + row * ld : nullptr;
   int r = rank_base, st = start_base;
   unsigned long long ties = 0;
-  int last_tied = 0;
   for (int c = 0; c < chunk; ++c) {
     int k = k0 + c;
     if (k < n) {
@@ -153,7 +150,6 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
       if (rrow) rrow[sample] = (uint16_t)r;
       if (srow) srow[k] = (uint16_t)st;
       ties += (unsigned long long)(k - st);
-      if (k > st) last_tied = k + 1;
     } else if (k < ld) {
       if (prow) prow[k] = (uint16_t)k;
       if (srow) srow[k] = (uint16_t)k;
@@ -170,25 +166,55 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
   if (rrow)
     for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)0x7FFF;
   atomicAdd(&s_n1, ties);
-  atomicMax(&s_tie_end, last_tied);
   __syncthreads();
   if (tid == 0) {
     if (n1_ws) n1_ws[row] = (int64_t)s_n1;
     if (n1_out) n1_out[row] = (int64_t)s_n1;
-    if (tie_end) tie_end[row] = s_tie_end;
   }
+  if (!runs) return;
+  // Pass 3: tie runs of length >= 2, in sorted order.  A thread owns the runs
+  // that start in its chunk; block scans give their index and the number of
+  // within-run pairs of all earlier runs.
+  auto key_at = [&](int k) { return s_keys[k] >> 16; };
+  int my_runs = 0, my_pairs = 0;
+  for (int c = 0; c < chunk; ++c) {
+    const int k = k0 + c;
+    if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
+      int e = k + 2;
+      while (e < n && key_at(e) == key_at(k)) ++e;
+      ++my_runs;
+      my_pairs += (e - k) * (e - k - 1) / 2;
+    }
+  }
+  int total_runs, total_pairs;
+  int run_idx = block_excl_sum(my_runs, s_scan, total_runs);
+  int pairs = block_excl_sum(my_pairs, s_scan, total_pairs);
+  uint64_t* rrow_runs = runs + row * (ld / 2);
+  for (int c = 0; c < chunk && my_runs > 0; ++c) {
+    const int k = k0 + c;
+    if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
+      int e = k + 2;
+      while (e < n && key_at(e) == key_at(k)) ++e;
+      const int len = e - k;
+      rrow_runs[run_idx++] =
+          ((uint64_t)(uint32_t)pairs << 32) | ((uint64_t)len << 16) | (uint64_t)k;
+      pairs += len * (len - 1) / 2;
+    }
+  }
+  if (tid == 0 && nruns) nruns[row] = total_runs;
 }
 
 __global__ void __launch_bounds__(kThreads)
 prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
                uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
-               int64_t* __restrict__ n1_out, int32_t* __restrict__ tie_end,
-               int32_t* __restrict__ status) {
+               int64_t* __restrict__ n1_out, int32_t* __restrict__ nruns,
+               uint64_t* __restrict__ runs, int32_t* __restrict__ status) {
   extern __shared__ uint64_t s_keys[];
   const int64_t row = blockIdx.x;
   if (row >= m) return;
-  prepass_row(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, tie_end, status, s_keys);
+  prepass_row(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+              s_keys);
 }
 
 // Every row of every matrix of a batch: block b ranks global row b, found by
@@ -210,7 +236,7 @@ prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
   while (npow2 < d.n) npow2 <<= 1;
   prepass_row(d.X, row, d.n, npow2, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
               (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
-              (int32_t*)d.rv.tie_end, (int32_t*)d.status, s_keys);
+              (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, s_keys);
 }
 
 }  // namespace
@@ -227,12 +253,12 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* tie_end, int32_t* status, hipStream_t s) {
+                          int32_t* nruns, uint64_t* runs, int32_t* status, hipStream_t s) {
   int npow2 = 64;
   while (npow2 < n) npow2 <<= 1;
   size_t lds = (size_t)npow2 * sizeof(uint64_t);
   hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)m), dim3(kThreads), lds, s, X, m, (int)n,
-                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, tie_end, status);
+                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status);
   return hipGetLastError();
 }
 
