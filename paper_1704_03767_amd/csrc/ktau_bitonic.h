@@ -26,11 +26,13 @@
 //
 // Partners at distance d:  d < K/2 -> another VGPR of the same lane (one
 // v_pk_min_u16 + one v_pk_max_u16 for two comparators);  d = K/2 -> the two
-// halves of one VGPR;  d >= K: another lane.  Lane distances 1..8 use
-// ds_swizzle; 16 and 32 use v_permlane16_swap / v_permlane32_swap, which
-// exchange half the lanes of two VGPRs so that the comparison becomes a plain
-// min/max between the two registers, and swap back; lane distances >= 64
-// (a 256-lane group) go through LDS.
+// halves of one VGPR;  d >= K: another lane.  Physical lane bits 0-3 use
+// ds_swizzle plus a masked select; bits 4 and 5 use v_permlane16_swap /
+// v_permlane32_swap, which exchange half the lanes of two VGPRs so that the
+// comparison becomes a plain min/max between the two registers (swapped back
+// afterwards); waves of a 256-lane group exchange through LDS.  In whole-wave
+// groups the two most used element lane bits (the lowest) are placed on
+// physical bits 4 and 5, which saves LDS swizzles.
 #pragma once
 
 #include "ktau_internal.h"
@@ -66,7 +68,25 @@ struct Net {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64 || G == 256,
                 "part of a wave, a wave or a 256-lane workgroup");
 
-  // Bit b of element (lane, j, h).
+  // Physical lane bit of element lane bit lb (measured: worth it for whole
+  // waves, not for 32-lane groups).
+  static constexpr int phys_bit(int lb) {
+    if constexpr (G >= 64) return lb == 0 ? 4 : lb == 1 ? 5 : lb < 6 ? lb - 2 : lb;
+    return lb;
+  }
+  // The element lane (the group's K-key block) held by physical lane `lane`.
+  static __device__ __forceinline__ int logical_lane(int lane) {
+    if constexpr (G < 64) {
+      return lane;
+    } else {
+      int l = 0;
+#pragma unroll
+      for (int b = 0; b < LOGG; ++b) l |= ((lane >> phys_bit(b)) & 1) << b;
+      return l;
+    }
+  }
+
+  // Bit b of element (lane, j, h); `lane` is the element lane.
   static __device__ __forceinline__ uint32_t ebit(int lane, int j, int h, int b) {
     const uint32_t e = ((uint32_t)lane << LOGK) | ((uint32_t)h << LOGKV) | (uint32_t)j;
     return (e >> b) & 1u;
@@ -79,9 +99,11 @@ struct Net {
     return (lo ? 0xFFFFu : 0u) | (hi ? 0xFFFF0000u : 0u);
   }
 
-  // One comparator stage on element bit k (partners e and e ^ 2^k).
+  // One comparator stage on element bit k (partners e and e ^ 2^k); `lane`
+  // is the element lane, `plane` the physical lane.
   template <int k>
-  static __device__ __forceinline__ void stage(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
+  static __device__ __forceinline__ void stage(u16x2 (&v)[KV], int lane, int plane,
+                                               uint32_t* xbuf) {
     if constexpr (k < LOGKV) {
 #pragma unroll
       for (int j = 0; j < KV; ++j) {
@@ -99,23 +121,24 @@ struct Net {
         v[j] = __builtin_shufflevector(mn, mx, 0, 3);
       }
     } else {
-      constexpr int lb = k - LOGK;            // lane bit
-      if constexpr (lb < 4) {
+      constexpr int lb = k - LOGK;            // element lane bit
+      constexpr int pb = phys_bit(lb);        // physical lane bit
+      if constexpr (pb < 4) {
         // the lower lane keeps the minimum; a bit mask in a VGPR selects it
         // (no per-lane condition has to live in scalar registers)
         const uint32_t keep_min = lane_mask(lane, lb);
 #pragma unroll
         for (int j = 0; j < KV; ++j) {
-          const u16x2 p = vec(lane_xor<(1 << lb)>(bits(v[j])));
+          const u16x2 p = vec(lane_xor<(1 << pb)>(bits(v[j])));
           const u16x2 mn = pmin(v[j], p), mx = pmax(v[j], p);
           v[j] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
         }
-      } else if constexpr (lb == 4 || lb == 5) {
+      } else if constexpr (pb == 4 || pb == 5) {
         if constexpr (KV >= 2) {
 #pragma unroll
           for (int j = 0; j < KV; j += 2) {
             uint32_t a = bits(v[j]), b = bits(v[j + 1]);
-            if constexpr (lb == 4) {
+            if constexpr (pb == 4) {
               auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
               a = s[0];
               b = s[1];
@@ -127,7 +150,7 @@ struct Net {
             const u16x2 mn = pmin(vec(a), vec(b)), mx = pmax(vec(a), vec(b));
             a = bits(mn);
             b = bits(mx);
-            if constexpr (lb == 4) {
+            if constexpr (pb == 4) {
               auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
               v[j] = vec(s[0]);
               v[j + 1] = vec(s[1]);
@@ -142,7 +165,7 @@ struct Net {
           const bool lower = ((lane >> lb) & 1) == 0;
           uint32_t a = bits(v[0]);
           uint32_t part;
-          if constexpr (lb == 4) {
+          if constexpr (pb == 4) {
             auto s = __builtin_amdgcn_permlane16_swap(a, a, false, false);
             part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
           } else {
@@ -157,11 +180,11 @@ struct Net {
         // across the waves of a 256-lane group, through LDS
         const uint32_t keep_min = lane_mask(lane, lb);
 #pragma unroll
-        for (int j = 0; j < KV; ++j) xbuf[j * G + lane] = bits(v[j]);
+        for (int j = 0; j < KV; ++j) xbuf[j * G + plane] = bits(v[j]);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < KV; ++j) {
-          const u16x2 p = vec(xbuf[j * G + (lane ^ (1 << lb))]);
+          const u16x2 p = vec(xbuf[j * G + (plane ^ (1 << pb))]);
           const u16x2 mn = pmin(v[j], p), mx = pmax(v[j], p);
           v[j] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
         }
@@ -171,9 +194,10 @@ struct Net {
   }
 
   template <int L, int k>
-  static __device__ __forceinline__ void stages_down(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
-    stage<k>(v, lane, xbuf);
-    if constexpr (k > 0) stages_down<L, k - 1>(v, lane, xbuf);
+  static __device__ __forceinline__ void stages_down(u16x2 (&v)[KV], int lane, int plane,
+                                                     uint32_t* xbuf) {
+    stage<k>(v, lane, plane, xbuf);
+    if constexpr (k > 0) stages_down<L, k - 1>(v, lane, plane, xbuf);
   }
 
   // Tag-and-orientation constant of level L for VGPR j: tag = bit L of e (the
@@ -221,9 +245,10 @@ struct Net {
   // Level L: its comparator stages, its count, and the re-tag for level L+1
   // (one AND, one dot product and one XOR per VGPR).
   template <int L>
-  static __device__ __forceinline__ void levels(u16x2 (&v)[KV], int lane, uint32_t* xbuf,
-                                                uint32_t& acc_in, uint32_t& total) {
-    stages_down<L, L>(v, lane, xbuf);
+  static __device__ __forceinline__ void levels(u16x2 (&v)[KV], int lane, int plane,
+                                                uint32_t* xbuf, uint32_t& acc_in,
+                                                uint32_t& total) {
+    stages_down<L, L>(v, lane, plane, xbuf);
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < KV; ++j) {
@@ -245,7 +270,7 @@ struct Net {
       const uint32_t all = (uint32_t)K * base + (uint32_t)(K * (K - 1) / 2);
       total += (all & (0u - desc)) - raw;
     }
-    if constexpr (L + 1 < LOGN) levels<L + 1>(v, lane, xbuf, acc_in, total);
+    if constexpr (L + 1 < LOGN) levels<L + 1>(v, lane, plane, xbuf, acc_in, total);
   }
 
   // Constant part of all levels: a level with nb >= 2 blocks of 2s adds
@@ -261,16 +286,18 @@ struct Net {
     return (uint32_t)c;
   }
 
-  // v: packed keys 2*rank (padding 0xFFFE), sorted in place.  Returns this
+  // v: packed keys 2*rank (padding 0xFFFE) of element lane logical_lane(plane),
+  // sorted in place; plane is the lane's index in the group.  Returns this
   // lane's share of the group's strict inversion count (the constant part is
   // added by lane 0 of the group), modulo 2^32.
-  static __device__ __forceinline__ uint32_t count(u16x2 (&v)[KV], int lane, uint32_t* xbuf) {
+  static __device__ __forceinline__ uint32_t count(u16x2 (&v)[KV], int plane, uint32_t* xbuf) {
+    const int lane = logical_lane(plane);
 #pragma unroll
     for (int j = 0; j < KV; ++j) v[j] = vec(bits(v[j]) ^ tag_const<0>(lane, j));
     uint32_t acc_in = 0, total = in_lane_const();
-    levels<0>(v, lane, xbuf, acc_in, total);
+    levels<0>(v, lane, plane, xbuf, acc_in, total);
     total -= acc_in;
-    if (lane == 0) total += constant_part();
+    if (plane == 0) total += constant_part();
     return total;
   }
 };

@@ -183,6 +183,71 @@ struct Deferred {
 
 // ======================================================= main (fast) path
 
+// One lane's walk over a stretch of the within-run pairs of u (positions in
+// u's sorted order, values 2 v' in an LDS row).  Pairs of a run are numbered
+// by the later position b, then the earlier a (index b(b-1)/2 + a), run after
+// run; a pair adds to xin when the earlier value is larger and to tie when
+// they are equal.
+struct TieWalk {
+  const uint64_t* rl;
+  int lo;                                  // current run
+  const uint16_t *pa, *pb, *ps, *pe;       // earlier, later, run start, run end
+  uint32_t me, o;                          // values at pb and pa
+
+  // Positions the walk at pair p (< the total number of pairs).
+  __device__ __forceinline__ void init(const uint64_t* runs, int nruns, uint32_t p,
+                                       const uint16_t* row) {
+    rl = runs;
+    int l = 0, h = nruns - 1;
+    while (l < h) {   // the last run whose pair prefix is <= p
+      const int mid = (l + h + 1) >> 1;
+      if ((uint32_t)(rl[mid] >> 32) <= p) l = mid;
+      else h = mid - 1;
+    }
+    lo = l;
+    const uint64_t e = rl[l];
+    const uint32_t start = (uint32_t)e & 0xFFFFu, len = (uint32_t)(e >> 16) & 0xFFFFu;
+    const uint32_t qi = p - (uint32_t)(e >> 32);
+    // b(b-1)/2 <= qi < b(b+1)/2 (a float estimate, then exact integer fix-up)
+    uint32_t b = (uint32_t)((1.0f + __fsqrt_rn(8.0f * (float)qi + 1.0f)) * 0.5f);
+    while (b * (b - 1) / 2 > qi) --b;
+    while (b * (b + 1) / 2 <= qi) ++b;
+    const uint32_t a = qi - b * (b - 1) / 2;
+    ps = row + start;
+    pe = ps + len;
+    pa = ps + a;
+    pb = ps + b;
+    me = *pb;
+    o = *pa;
+  }
+
+  // Counts the current pair and moves to the next; `more` tells whether
+  // another pair follows (then the next run exists when this one ends).  The
+  // move to the next later position is branch-free (it happens every few
+  // steps in some lane); only the end of a run branches.
+  __device__ __forceinline__ void step(const uint16_t* row, bool more, uint32_t& xin,
+                                       uint32_t& tie) {
+    const uint32_t cur = o;
+    xin += cur > me ? 1u : 0u;
+    tie += cur == me ? 1u : 0u;
+    ++pa;
+    const bool wrap = pa == pb;
+    pb = wrap ? pb + 1 : pb;
+    pa = wrap ? ps : pa;
+    if (pb == pe) {
+      if (more) {
+        const uint64_t e = rl[++lo];
+        ps = row + ((uint32_t)e & 0xFFFFu);
+        pe = ps + ((uint32_t)(e >> 16) & 0xFFFFu);
+      }
+      pa = ps;
+      pb = ps + 1;
+    }
+    me = *pb;
+    o = *pa;   // pa < pb: inside the row
+  }
+};
+
 // LDS words per group: the v rank row (uint16), reused for v' on the tie
 // path, plus the network's exchange buffer for 256-lane groups.
 template <int K, int G>
@@ -212,7 +277,8 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
   const int64_t u = swap ? x : y, v = swap ? y : x;
   const int64_t n1u = swap ? n1x : n1y;
   const int64_t ld = ry.ld;
-  const int k0 = lane * K;
+  // this lane holds sorted positions k0 .. k0+K-1 (the network's element lane)
+  const int k0 = Net::logical_lane(lane) * K;
   // vector loads stay inside the row (ld is a multiple of 64, so a lane is
   // either wholly inside or wholly past n)
   const bool in_row = k0 + K <= ld;
@@ -268,59 +334,22 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
     }
     group_sync<G>();
     // The n1_u pairs of positions inside one tie run of u (Step 2), split
-    // evenly among the lanes: lane l takes pairs [l c, (l+1) c) of the
-    // sequence that numbers a run's pairs by the later position b, then the
-    // earlier a (index b(b-1)/2 + a), run after run.  Each pair adds to X
-    // when the earlier v' is larger and to n3 when they are equal.
+    // evenly into 2G stretches; lane l walks stretches l and l + G side by
+    // side so that the LDS loads of the two walks overlap.
     const uint64_t* rl = ru_v.runs + u * (ld / 2);
+    const int nr = ru_v.nruns[u];
     const uint32_t total = (uint32_t)n1u;
-    const uint32_t per = (total + G - 1) / G;
-    uint32_t p = (uint32_t)lane * per;
-    const uint32_t cnt = p < total ? (total - p < per ? total - p : per) : 0u;
-    if (cnt > 0) {
-      // the run holding pair p: the last run whose pair prefix is <= p
-      int lo = 0, hi = ru_v.nruns[u] - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((uint32_t)(rl[mid] >> 32) <= p) lo = mid;
-        else hi = mid - 1;
-      }
-      const uint64_t e = rl[lo];
-      const uint32_t start = (uint32_t)e & 0xFFFFu, len = (uint32_t)(e >> 16) & 0xFFFFu;
-      const uint32_t qi = p - (uint32_t)(e >> 32);
-      // b(b-1)/2 <= qi < b(b+1)/2 (a float estimate, then exact integer fix-up)
-      uint32_t b = (uint32_t)((1.0f + __fsqrt_rn(8.0f * (float)qi + 1.0f)) * 0.5f);
-      while (b * (b - 1) / 2 > qi) --b;
-      while (b * (b + 1) / 2 <= qi) ++b;
-      const uint32_t a = qi - b * (b - 1) / 2;
-      // byte offsets in the LDS row: earlier position, later position, run
-      // start and end; the next earlier value is loaded one step ahead
-      const char* rb = (const char*)row;
-      uint32_t oa = 2 * (start + a), ob = 2 * (start + b);
-      uint32_t os = 2 * start, oe = 2 * (start + len);
-      uint32_t me = *(const uint16_t*)(rb + ob);
-      uint32_t o = *(const uint16_t*)(rb + oa);
-      for (uint32_t left = cnt; left > 0; --left) {
-        const uint32_t cur = o;
-        oa += 2;
-        o = *(const uint16_t*)(rb + oa);   // oa <= ob: inside the row
-        xin += cur > me ? 1u : 0u;
-        tie += cur == me ? 1u : 0u;
-        if (oa == ob) {
-          ob += 2;
-          if (ob == oe) {
-            // next run; it exists whenever pairs remain
-            if (left > 1) {
-              const uint64_t e2 = rl[++lo];
-              os = 2 * ((uint32_t)e2 & 0xFFFFu);
-              oe = os + 2 * ((uint32_t)(e2 >> 16) & 0xFFFFu);
-            }
-            ob = os + 2;
-          }
-          oa = os;
-          me = *(const uint16_t*)(rb + ob);
-          o = *(const uint16_t*)(rb + oa);
-        }
+    const uint32_t per = (total + 2 * G - 1) / (2 * G);
+    const uint32_t p0 = (uint32_t)lane * per, p1 = (uint32_t)(lane + G) * per;
+    const uint32_t c0 = p0 < total ? (total - p0 < per ? total - p0 : per) : 0u;
+    const uint32_t c1 = p1 < total ? (total - p1 < per ? total - p1 : per) : 0u;
+    if (c0 > 0) {
+      TieWalk w0, w1;
+      w0.init(rl, nr, p0, row);
+      if (c1 > 0) w1.init(rl, nr, p1, row);
+      for (uint32_t i = 0; i < c0; ++i) {
+        w0.step(row, i + 1 < c0, xin, tie);
+        if (i < c1) w1.step(row, i + 1 < c1, xin, tie);
       }
     }
   }
