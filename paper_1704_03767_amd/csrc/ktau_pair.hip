@@ -19,22 +19,21 @@
 // bitonic network of ktau_bitonic.h.  The composite pass uses an LDS merge
 // path with 32-bit keys.  Keeping it in its own kernel keeps the register
 // budget of the main kernels small.
+#include "ktau_order.h"
 #include "ktau_pairdev.h"
 
 namespace ktau {
 namespace {
 
-// One q x q tile (Eq. 11-14) of a matrix; its pairs go to the waves
-// round-robin (G = 64) or one after another to the whole workgroup (G = 256).
+// One q x q tile (Eq. 11-14) of a matrix, tile coordinates (yq, xq); its
+// pairs go to the workgroup's groups round-robin.
 template <int K, int G>
-__device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t t, uint32_t* lds_all,
-                                           uint32_t* red) {
+__device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t yq, int64_t xq,
+                                           uint32_t* lds_all, uint32_t* red) {
   constexpr int kGroups = kBlock / G;
   const int group = threadIdx.x / G;
   const int lane = threadIdx.x % G;
   uint32_t* lds = lds_all + group * FastLds<K, G>::kWords;
-  int64_t yq, xq;
-  tile_coord(d.w, t, yq, xq);
   const int q = d.q;
   const int64_t budget = direct_budget(d.n);
   Deferred<G> done;
@@ -49,13 +48,24 @@ __device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t t, uint32_t
   done.flush(lane, d.out, d.n);
 }
 
-// Plain launch, tile order.
+// Plain launch over the tiles.  With one workgroup per tile the tiles follow
+// the XCD-aware band schedule (input rows reused from L2); otherwise a grid
+// stride over the tile ids.
 template <int K, int G>
 __global__ void __launch_bounds__(kBlock) pairs_tiles_kernel(MatDesc d) {
   __shared__ uint32_t lds[(kBlock / G) * FastLds<K, G>::kWords];
   __shared__ uint32_t red[kWavesPerBlock];
   if (*d.status != 0) return;
-  for (int64_t t = blockIdx.x; t < d.n_units; t += gridDim.x) tile_pairs<K, G>(d, t, lds, red);
+  int64_t yq, xq;
+  if ((int64_t)gridDim.x == d.n_units) {
+    scheduled_tile(d.w, d.n_units, blockIdx.x, yq, xq);
+    tile_pairs<K, G>(d, yq, xq, lds, red);
+    return;
+  }
+  for (int64_t t = blockIdx.x; t < d.n_units; t += gridDim.x) {
+    tile_coord(d.w, t, yq, xq);
+    tile_pairs<K, G>(d, yq, xq, lds, red);
+  }
 }
 
 // Plain launch, job order: strict job ids [J_begin, J_end), one per group.
@@ -109,7 +119,9 @@ pairs_persistent_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_
       if (unit_prefix[mid] <= unit) lo = mid;
       else hi = mid - 1;
     }
-    tile_pairs<K, G>(descs[lo], unit - unit_prefix[lo], lds, red);
+    int64_t yq, xq;
+    tile_coord(descs[lo].w, unit - unit_prefix[lo], yq, xq);
+    tile_pairs<K, G>(descs[lo], yq, xq, lds, red);
   }
 }
 
