@@ -183,7 +183,7 @@ struct ClassRun {
   int64_t first, count;          // slice of the descriptor table
   int64_t total_units;
   int64_t* prefix = nullptr;     // device [count + 1], unit prefix inside the class
-  int64_t* counter = nullptr;    // device tile counter
+  int64_t* counters = nullptr;   // device: 8 tile counters (one per XCD stretch)
   hipStream_t stream = nullptr;  // branch stream (default priority)
   hipEvent_t done = nullptr;
 };
@@ -197,6 +197,7 @@ struct ktau_batch {
   MatDesc* descs = nullptr;          // device, class-sorted
   int64_t* row_prefix = nullptr;     // device [count + 1]
   int32_t* words = nullptr;          // device: [0] status; int64 counters from byte 64
+  int clear_count = 0;               // int32 words cleared before a run
   int64_t total_rows = 0;
   int max_n = 0;
   bool use_graph = true;
@@ -208,12 +209,10 @@ struct ktau_batch {
 
 namespace {
 
-constexpr int kClearWords = 32;      // status word + up to 7 int64 counters
-
 // The whole run on stream s: the scheme classes fork onto their own streams
 // after the pre-pass and join before the tie passes.
 int enqueue_batch(ktau_batch* b, hipStream_t s) {
-  if (clear_words(b->words, kClearWords, s) != KTAU_OK) return KTAU_EDEVICE;
+  if (clear_words(b->words, b->clear_count, s) != KTAU_OK) return KTAU_EDEVICE;
   if (launch_prepass_batch(b->descs, b->count, b->total_rows, b->row_prefix, b->max_n, s) !=
       hipSuccess)
     return KTAU_EDEVICE;
@@ -221,7 +220,7 @@ int enqueue_batch(ktau_batch* b, hipStream_t s) {
   for (ClassRun& c : b->classes) {
     if (hipStreamWaitEvent(c.stream, b->fork, 0) != hipSuccess) return KTAU_EDEVICE;
     if (launch_pairs_persistent(c.scheme, b->descs + c.first, c.count, c.total_units, c.prefix,
-                                c.counter, b->words, c.stream) != hipSuccess)
+                                c.counters, b->words, c.stream) != hipSuccess)
       return KTAU_EDEVICE;
     if (hipEventRecord(c.done, c.stream) != hipSuccess) return KTAU_EDEVICE;
   }
@@ -308,8 +307,10 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
     b->classes.back().count++;
   }
   const int64_t ncls = (int64_t)b->classes.size();
-  // arena: words | descs | row prefix | class unit prefixes | workspaces
-  size_t off = 256;
+  // arena: words (status, then 8 tile counters per class) | descs | row
+  // prefix | class unit prefixes | workspaces
+  const size_t words_bytes = 64 + (size_t)ncls * 8 * sizeof(int64_t);
+  size_t off = (size_t)round_up((int64_t)words_bytes, (int64_t)kAlign);
   const size_t desc_off = off;
   off = (size_t)round_up((int64_t)(off + (size_t)count * sizeof(MatDesc)), (int64_t)kAlign);
   const size_t rp_off = off;
@@ -327,6 +328,7 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
     return KTAU_ENOMEM;
   }
   b->words = (int32_t*)b->arena;
+  b->clear_count = (int)(words_bytes / sizeof(int32_t));
   b->descs = (MatDesc*)(b->arena + desc_off);
   b->row_prefix = (int64_t*)(b->arena + rp_off);
   int64_t* up_dev = (int64_t*)(b->arena + up_off);
@@ -336,7 +338,7 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
   for (int64_t c = 0; c < ncls; ++c) {
     ClassRun& cr = b->classes[c];
     cr.prefix = up_dev + cr.first + c;
-    cr.counter = (int64_t*)(b->arena + 64) + c;
+    cr.counters = (int64_t*)(b->arena + 64) + 8 * c;
     int64_t acc = 0;
     uprefix.push_back(0);
     for (int64_t p = cr.first; p < cr.first + cr.count; ++p) {

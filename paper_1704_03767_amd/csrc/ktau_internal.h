@@ -176,10 +176,11 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s);
 
 // Persistent launch of one scheme over the tiles of the matrices of a
-// descriptor table (all of that scheme), taking tiles from *counter_dev.
+// descriptor table (all of that scheme), taking tiles from the kXcds (8)
+// zeroed int64 counters at counters_dev.
 hipError_t launch_pairs_persistent(int scheme, const MatDesc* descs_dev, int64_t count,
                                    int64_t total_units, const int64_t* unit_prefix_dev,
-                                   int64_t* counter_dev, const int32_t* status, hipStream_t s);
+                                   int64_t* counters_dev, const int32_t* status, hipStream_t s);
 
 // Heavy-row lists and the composite pass for every matrix of a table.
 hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, hipStream_t s);

@@ -94,24 +94,32 @@ __global__ void __launch_bounds__(kBlock) pairs_jobs_kernel(MatDesc d) {
 }
 
 // Persistent launch over the concatenated tile spaces of the matrices of one
-// scheme class.  Units (tiles) are taken from an atomic counter; a unit is
-// located by binary search on the per-matrix unit prefix, then Eq. 13-14
-// inside its matrix.
+// scheme class.  The unit (tile) space is cut into kXcds contiguous
+// stretches; workgroup b serves stretch b mod kXcds (the XCD it runs on),
+// taking units from that stretch's atomic counter, so each XCD works
+// through consecutive units.  A unit is located by binary search on the
+// per-matrix unit prefix, and inside its matrix the units follow the band
+// order (input rows reused from the XCD's L2).
 template <int K, int G>
 __global__ void __launch_bounds__(kBlock)
 pairs_persistent_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_t total_units,
-                        const int64_t* __restrict__ unit_prefix, int64_t* __restrict__ counter,
+                        const int64_t* __restrict__ unit_prefix, int64_t* __restrict__ counters,
                         const int32_t* __restrict__ status) {
   __shared__ uint32_t lds[(kBlock / G) * FastLds<K, G>::kWords];
   __shared__ uint32_t red[kWavesPerBlock];
   __shared__ int64_t s_unit;
   if (*status != 0) return;
+  const int64_t x = blockIdx.x % kXcds;
+  const int64_t per = total_units / kXcds, rem = total_units % kXcds;
+  const int64_t first = x * per + (x < rem ? x : rem);
+  const int64_t len = per + (x < rem ? 1 : 0);
   for (;;) {
-    if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd((unsigned long long*)counter, 1ull);
+    if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd((unsigned long long*)(counters + x), 1ull);
     __syncthreads();
-    const int64_t unit = s_unit;
+    const int64_t k = s_unit;
     __syncthreads();
-    if (unit >= total_units) break;
+    if (k >= len) break;
+    const int64_t unit = first + k;
     // matrix b with unit_prefix[b] <= unit < unit_prefix[b + 1]
     int64_t lo = 0, hi = count - 1;
     while (lo < hi) {
@@ -120,7 +128,7 @@ pairs_persistent_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_
       else hi = mid - 1;
     }
     int64_t yq, xq;
-    tile_coord(descs[lo].w, unit - unit_prefix[lo], yq, xq);
+    band_tile(descs[lo].w, unit - unit_prefix[lo], yq, xq);
     tile_pairs<K, G>(descs[lo], yq, xq, lds, red);
   }
 }
@@ -295,7 +303,7 @@ hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
 
 template <int K, int G>
 hipError_t persistent_t(const MatDesc* descs, int64_t count, int64_t total_units,
-                        const int64_t* prefix, int64_t* counter, const int32_t* status,
+                        const int64_t* prefix, int64_t* counters, const int32_t* status,
                         hipStream_t s) {
   // occupancy is queried once per scheme (first call, outside any capture)
   static const int per_cu = [] {
@@ -310,16 +318,16 @@ hipError_t persistent_t(const MatDesc* descs, int64_t count, int64_t total_units
   if (grid > total_units) grid = total_units;
   if (grid < 1) return hipSuccess;
   hipLaunchKernelGGL((pairs_persistent_kernel<K, G>), dim3((unsigned)grid), dim3(kBlock), 0, s,
-                     descs, count, total_units, prefix, counter, status);
+                     descs, count, total_units, prefix, counters, status);
   return hipGetLastError();
 }
 
 hipError_t launch_pairs_persistent(int scheme, const MatDesc* d, int64_t count, int64_t total,
-                                   const int64_t* prefix, int64_t* counter, const int32_t* status,
-                                   hipStream_t s) {
+                                   const int64_t* prefix, int64_t* counters,
+                                   const int32_t* status, hipStream_t s) {
   switch (scheme) {
 #define KTAU_CASE(S, K, G) \
-  case S: return persistent_t<K, G>(d, count, total, prefix, counter, status, s);
+  case S: return persistent_t<K, G>(d, count, total, prefix, counters, status, s);
     KTAU_FOR_EACH_SCHEME(KTAU_CASE)
 #undef KTAU_CASE
     default: return hipErrorInvalidValue;
