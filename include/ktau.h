@@ -198,8 +198,9 @@ void ktau_batch_default_opts(ktau_batch_opts* opts_host);
  * plan's device arena (rank workspaces for all matrices plus descriptors;
  * about 6 m ceil64(n) bytes per matrix).  The matrices' X_dev and output
  * arrays are the caller's and must stay valid while the plan is used.
- * Autotuning, when a sample-count class is not yet tuned, runs timing
- * launches on `stream` and blocks until they finish. */
+ * Autotuning, when a sample-count class is not yet tuned, times the
+ * candidates on the first rows of the class's matrix with the most rows
+ * (launches on `stream`, blocking until they finish). */
 int ktau_batch_create(const ktau_matrix* mats_host, int64_t count,
                       const ktau_batch_opts* opts_host, void* stream,
                       ktau_batch** plan_out);
@@ -217,8 +218,9 @@ int ktau_batch_plan(const ktau_batch* plan, int64_t i, int32_t* scheme_host,
 void ktau_batch_destroy(ktau_batch* plan);
 
 /* Autotuner: for each n in ns_host, the (scheme, q) the batch planner would
- * use, tuning any class not yet in the process table or the cache file
- * (timing launches on `stream`, synchronous). */
+ * use, tuning any class not yet in the process table or the cache file on a
+ * synthetic matrix with a zero tie run in every row (timing launches on
+ * `stream`, synchronous). */
 int ktau_autotune(const int64_t* ns_host, int64_t count, const char* cache_path,
                   void* stream, int32_t* schemes_out_host, int32_t* q_out_host);
 

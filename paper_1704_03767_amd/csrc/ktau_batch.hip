@@ -7,10 +7,12 @@
 // (tile) and row prefixes.  One run is: clear status and tile counters; one
 // pre-pass launch over every row of every matrix; for each scheme class
 // present, one persistent pair launch whose workgroups take tiles of any
-// matrix of the class from an atomic counter (Sec. 4.1 notes a shared counter
-// balances jobs of varied cost) -- the classes run as parallel branches, each
-// kernel with its own register budget; then the heavy-row and composite
-// passes.  The sequence is captured once in a hipGraph and replayed.
+// matrix of the class from atomic counters (Sec. 4.1 notes a shared counter
+// balances jobs of varied cost), each kernel with its own register budget;
+// the classes run one after another, the most work first (measured: class
+// kernels running side by side on parallel streams slow each other down by
+// about 10%); then the heavy-row and composite passes.  The sequence is
+// captured once in a hipGraph and replayed.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -74,7 +76,9 @@ void save_cache(const char* path) {
   rename(tmp.c_str(), path);
 }
 
-// Deterministic tie-free test matrix for timing (splitmix64 of the index).
+// Deterministic timing matrix when no data is at hand (splitmix64 of the
+// index): uniform values with about 1.6% exact zeros, a tie run in every row
+// as in zero-inflated expression data.
 __global__ void synth_kernel(float* X, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -82,7 +86,14 @@ __global__ void synth_kernel(float* X, int64_t count) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   z ^= z >> 31;
-  X[i] = (float)(z >> 40) * (1.0f / 16777216.0f);
+  X[i] = (z & 63u) == 0 ? 0.0f : (float)(z >> 40) * (1.0f / 16777216.0f);
+}
+
+// Rows of the timing matrix for n samples: about 2^31 merge steps in total,
+// so that one candidate's launch takes milliseconds.
+int64_t tune_rows(int64_t n) {
+  const int64_t m = (int64_t)sqrt(4.0e9 / (double)n);
+  return m < 256 ? 256 : m;
 }
 
 // Candidate schemes for a class: those that hold the class without more
@@ -94,10 +105,14 @@ std::vector<int> candidates(int64_t cls) {
   return v;
 }
 
-// Measures every (scheme, q) candidate of class `cls` on a synthetic matrix
-// of m_t x cls and records the fastest.
-int tune_class(int64_t cls, hipStream_t s) {
-  const int64_t n = cls, m = 768;
+// Measures every (scheme, q) candidate of class `cls` and records the
+// fastest.  The timing matrix is the first rows of `src` (m_src x n_src, a
+// matrix of the class from the caller's batch) when given, else a synthetic
+// cls-sample matrix.
+int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipStream_t s) {
+  const int64_t n = src ? n_src : cls;
+  int64_t m = tune_rows(n);
+  if (src && m > m_src) m = m_src;
   const WsLayout L = ws_layout(m, n);
   float* X = nullptr;
   void* ws = nullptr;
@@ -105,17 +120,18 @@ int tune_class(int64_t cls, hipStream_t s) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = KTAU_OK;
   const int64_t P = m * (m - 1) / 2;
-  if (hipMalloc(&X, (size_t)(m * n) * sizeof(float)) != hipSuccess ||
+  if ((!src && hipMalloc(&X, (size_t)(m * n) * sizeof(float)) != hipSuccess) ||
       hipMalloc(&ws, L.total) != hipSuccess || hipMalloc(&tau, (size_t)P * sizeof(double)) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     rc = KTAU_ENOMEM;
   }
   Plan best{default_scheme(n), 8, 0.0};
   if (rc == KTAU_OK) {
-    hipLaunchKernelGGL(synth_kernel, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, X,
-                       m * n);
+    if (!src)
+      hipLaunchKernelGGL(synth_kernel, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, X,
+                         m * n);
     if (hipGetLastError() != hipSuccess || clear_words((int32_t*)ws, 2, s) != KTAU_OK ||
-        prepass_ws(X, m, n, ws, nullptr, nullptr, s) != KTAU_OK)
+        prepass_ws(src ? src : X, m, n, ws, nullptr, nullptr, s) != KTAU_OK)
       rc = KTAU_EDEVICE;
   }
   if (rc == KTAU_OK) {
@@ -151,7 +167,10 @@ int tune_class(int64_t cls, hipStream_t s) {
   return rc;
 }
 
-Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* rc) {
+// The plan of a matrix with n samples; a class not yet tuned is tuned on
+// rep (m_rep x n_rep, may be NULL: synthetic data).
+Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* rc,
+              const float* rep = nullptr, int64_t m_rep = 0, int64_t n_rep = 0) {
   const int64_t cls = n_class(n);
   if (!autotune) return Plan{default_scheme(n), env_int("KTAU_TILE_Q", 8), 0.0};
   std::lock_guard<std::mutex> g(g_tune_mu);
@@ -161,7 +180,7 @@ Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* r
     it = g_tuned.find(cls);
   }
   if (it == g_tuned.end()) {
-    *rc = tune_class(cls, s);
+    *rc = tune_class(cls, rep, m_rep, n_rep, s);
     if (*rc != KTAU_OK) return Plan{default_scheme(n), 8, 0.0};
     save_cache(cache);
     it = g_tuned.find(cls);
@@ -177,15 +196,14 @@ Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* r
 using namespace ktau;
 
 // One scheme class of a batch: a contiguous slice of the descriptor table,
-// launched as its own persistent kernel on its own branch of the graph.
+// launched as its own persistent kernel.
 struct ClassRun {
   int scheme;
   int64_t first, count;          // slice of the descriptor table
   int64_t total_units;
+  double work = 0.0;             // estimated cost: pairs x network size
   int64_t* prefix = nullptr;     // device [count + 1], unit prefix inside the class
   int64_t* counters = nullptr;   // device: 8 tile counters (one per XCD stretch)
-  hipStream_t stream = nullptr;  // branch stream (default priority)
-  hipEvent_t done = nullptr;
 };
 
 struct ktau_batch {
@@ -201,7 +219,6 @@ struct ktau_batch {
   int64_t total_rows = 0;
   int max_n = 0;
   bool use_graph = true;
-  hipEvent_t fork = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -209,23 +226,16 @@ struct ktau_batch {
 
 namespace {
 
-// The whole run on stream s: the scheme classes fork onto their own streams
-// after the pre-pass and join before the tie passes.
+// The whole run on stream s.
 int enqueue_batch(ktau_batch* b, hipStream_t s) {
   if (clear_words(b->words, b->clear_count, s) != KTAU_OK) return KTAU_EDEVICE;
   if (launch_prepass_batch(b->descs, b->count, b->total_rows, b->row_prefix, b->max_n, s) !=
       hipSuccess)
     return KTAU_EDEVICE;
-  if (hipEventRecord(b->fork, s) != hipSuccess) return KTAU_EDEVICE;
-  for (ClassRun& c : b->classes) {
-    if (hipStreamWaitEvent(c.stream, b->fork, 0) != hipSuccess) return KTAU_EDEVICE;
+  for (const ClassRun& c : b->classes)
     if (launch_pairs_persistent(c.scheme, b->descs + c.first, c.count, c.total_units, c.prefix,
-                                c.counters, b->words, c.stream) != hipSuccess)
+                                c.counters, b->words, s) != hipSuccess)
       return KTAU_EDEVICE;
-    if (hipEventRecord(c.done, c.stream) != hipSuccess) return KTAU_EDEVICE;
-  }
-  for (ClassRun& c : b->classes)
-    if (hipStreamWaitEvent(s, c.done, 0) != hipSuccess) return KTAU_EDEVICE;
   if (launch_tie_passes_batch(b->descs, b->count, s) != hipSuccess) return KTAU_EDEVICE;
   return KTAU_OK;
 }
@@ -234,11 +244,6 @@ void free_batch(ktau_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  for (ClassRun& c : b->classes) {
-    if (c.stream) (void)hipStreamDestroy(c.stream);
-    if (c.done) (void)hipEventDestroy(c.done);
-  }
-  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->arena) (void)hipFree(b->arena);
   delete b;
 }
@@ -275,11 +280,19 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
   const hipStream_t s = (hipStream_t)stream;
   const char* cache = o.tune_cache ? o.tune_cache : getenv("KTAU_TUNE_CACHE");
 
-  // plans, then the class-sorted order
+  // plans (a class still to be tuned is timed on its matrix with the most
+  // pairs), then the class-sorted order
+  std::map<int64_t, int64_t> rep;   // n class -> matrix index
+  for (int64_t i = 0; i < count; ++i) {
+    auto it = rep.find(n_class(mats[i].n));
+    if (it == rep.end() || mats[i].m > mats[it->second].m) rep[n_class(mats[i].n)] = i;
+  }
   std::vector<Plan> plans(count);
   for (int64_t i = 0; i < count; ++i) {
     int rc = KTAU_OK;
-    plans[i] = plan_for(mats[i].n, o.autotune != 0 && o.force_scheme < 0, cache, s, &rc);
+    const ktau_matrix& r = mats[rep[n_class(mats[i].n)]];
+    plans[i] = plan_for(mats[i].n, o.autotune != 0 && o.force_scheme < 0, cache, s, &rc, r.X_dev,
+                        r.m, r.n);
     if (rc != KTAU_OK) return rc;
     if (o.force_scheme >= 0) plans[i].scheme = o.force_scheme;
     if (o.force_q > 0) plans[i].q = o.force_q;
@@ -351,6 +364,7 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
       d.unit_begin = acc;
       acc += d.n_units;
       uprefix.push_back(acc);
+      cr.work += (double)(mt.m * (mt.m - 1) / 2) * (double)scheme_capacity(pl.scheme);
       rprefix[p + 1] = rprefix[p] + mt.m;
       b->host_descs[p] = d;
       b->max_n = std::max(b->max_n, (int)mt.n);
@@ -365,14 +379,9 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(up_dev, uprefix.data(), uprefix.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
     rc = KTAU_EDEVICE;
-  if (rc == KTAU_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
-    rc = KTAU_EDEVICE;
-  for (ClassRun& c : b->classes) {
-    if (rc != KTAU_OK) break;
-    if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess)
-      rc = KTAU_EDEVICE;
-  }
+  // the most work first
+  std::stable_sort(b->classes.begin(), b->classes.end(),
+                   [](const ClassRun& a, const ClassRun& c) { return a.work > c.work; });
   // query each class kernel's occupancy now, outside any capture
   for (ClassRun& c : b->classes) {
     if (rc != KTAU_OK) break;
@@ -392,7 +401,7 @@ int ktau_batch_run(ktau_batch* b, void* stream) {
   if (!b) return KTAU_EINVAL;
   const hipStream_t s = (hipStream_t)stream;
   if (!b->use_graph) return enqueue_batch(b, s);
-  // first run: capture the whole sequence (with its fork/join branches) once
+  // first run: capture the whole sequence once
   if (!b->exec) {
     if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return KTAU_EDEVICE;

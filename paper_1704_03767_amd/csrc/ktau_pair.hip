@@ -26,18 +26,19 @@ namespace ktau {
 namespace {
 
 // One q x q tile (Eq. 11-14) of a matrix, tile coordinates (yq, xq); its
-// pairs go to the workgroup's groups round-robin.
+// pairs go round-robin to the `workers` groups that run it, this thread's
+// group being number `worker` among them.
 template <int K, int G>
 __device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t yq, int64_t xq,
-                                           uint32_t* lds_all, uint32_t* red) {
-  constexpr int kGroups = kBlock / G;
+                                           uint32_t* lds_all, uint32_t* red, int worker,
+                                           int workers) {
   const int group = threadIdx.x / G;
   const int lane = threadIdx.x % G;
   uint32_t* lds = lds_all + group * FastLds<K, G>::kWords;
   const int q = d.q;
   const int64_t budget = direct_budget(d.n);
   Deferred<G> done;
-  for (int p = group; p < q * q; p += kGroups) {
+  for (int p = worker; p < q * q; p += workers) {
     const int64_t y = yq * q + p / q, x = xq * q + p % q;
     if (y >= x || x >= d.m) continue;
     uint32_t nd, n3;
@@ -52,28 +53,31 @@ __device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t yq, int64_t
 // the XCD-aware band schedule (input rows reused from L2); otherwise a grid
 // stride over the tile ids.
 template <int K, int G>
-__global__ void __launch_bounds__(kBlock) pairs_tiles_kernel(MatDesc d) {
-  __shared__ uint32_t lds[(kBlock / G) * FastLds<K, G>::kWords];
-  __shared__ uint32_t red[kWavesPerBlock];
+__global__ void __launch_bounds__(kBlock, (fast_waves<K, G>())) pairs_tiles_kernel(MatDesc d) {
+  using FL = FastLds<K, G>;
+  __shared__ uint32_t lds[FL::kBlockWords];
+  uint32_t* red = FL::red(lds);
   if (*d.status != 0) return;
+  const int group = threadIdx.x / G;
   int64_t yq, xq;
   if ((int64_t)gridDim.x == d.n_units) {
     scheduled_tile(d.w, d.n_units, blockIdx.x, yq, xq);
-    tile_pairs<K, G>(d, yq, xq, lds, red);
+    tile_pairs<K, G>(d, yq, xq, lds, red, group, FL::kGroups);
     return;
   }
   for (int64_t t = blockIdx.x; t < d.n_units; t += gridDim.x) {
     tile_coord(d.w, t, yq, xq);
-    tile_pairs<K, G>(d, yq, xq, lds, red);
+    tile_pairs<K, G>(d, yq, xq, lds, red, group, FL::kGroups);
   }
 }
 
 // Plain launch, job order: strict job ids [J_begin, J_end), one per group.
 template <int K, int G>
-__global__ void __launch_bounds__(kBlock) pairs_jobs_kernel(MatDesc d) {
-  constexpr int kGroups = kBlock / G;
-  __shared__ uint32_t lds[kGroups * FastLds<K, G>::kWords];
-  __shared__ uint32_t red[kWavesPerBlock];
+__global__ void __launch_bounds__(kBlock, (fast_waves<K, G>())) pairs_jobs_kernel(MatDesc d) {
+  using FL = FastLds<K, G>;
+  constexpr int kGroups = FL::kGroups;
+  __shared__ uint32_t lds[FL::kBlockWords];
+  uint32_t* red = FL::red(lds);
   if (*d.status != 0) return;
   const int group = threadIdx.x / G;
   const int lane = threadIdx.x % G;
@@ -95,30 +99,55 @@ __global__ void __launch_bounds__(kBlock) pairs_jobs_kernel(MatDesc d) {
 
 // Persistent launch over the concatenated tile spaces of the matrices of one
 // scheme class.  The unit (tile) space is cut into kXcds contiguous
-// stretches; workgroup b serves stretch b mod kXcds (the XCD it runs on),
+// stretches; workgroup b starts on stretch b mod kXcds (the XCD it runs on),
 // taking units from that stretch's atomic counter, so each XCD works
-// through consecutive units.  A unit is located by binary search on the
+// through consecutive units; a worker whose stretch is used up moves on to
+// the following stretches, which keeps the load balanced when workgroups
+// start late (other kernels of the batch hold the CUs).  With groups of up to
+// 64 lanes every wave is a
+// worker of its own (no workgroup-wide hand-off of units); 256-lane groups
+// take units per workgroup.  A unit is located by binary search on the
 // per-matrix unit prefix, and inside its matrix the units follow the band
 // order (input rows reused from the XCD's L2).
 template <int K, int G>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (fast_waves<K, G>()))
 pairs_persistent_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_t total_units,
                         const int64_t* __restrict__ unit_prefix, int64_t* __restrict__ counters,
                         const int32_t* __restrict__ status) {
-  __shared__ uint32_t lds[(kBlock / G) * FastLds<K, G>::kWords];
-  __shared__ uint32_t red[kWavesPerBlock];
-  __shared__ int64_t s_unit;
+  using FL = FastLds<K, G>;
+  __shared__ uint32_t lds[FL::kBlockWords];
+  uint32_t* red = FL::red(lds);
   if (*status != 0) return;
-  const int64_t x = blockIdx.x % kXcds;
   const int64_t per = total_units / kXcds, rem = total_units % kXcds;
-  const int64_t first = x * per + (x < rem ? x : rem);
-  const int64_t len = per + (x < rem ? 1 : 0);
-  for (;;) {
-    if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd((unsigned long long*)(counters + x), 1ull);
-    __syncthreads();
-    const int64_t k = s_unit;
-    __syncthreads();
-    if (k >= len) break;
+  constexpr bool kWaveWorkers = G <= 64;
+  const int worker = kWaveWorkers ? (int)(threadIdx.x & 63) / G : 0;
+  const int workers = kWaveWorkers ? 64 / G : 1;
+  int64_t x = blockIdx.x % kXcds;
+  int64_t first = x * per + (x < rem ? x : rem);
+  int64_t len = per + (x < rem ? 1 : 0);
+  for (int visited = 0;;) {
+    int64_t k;
+    if constexpr (kWaveWorkers) {
+      // lane 0 of the wave takes the unit; every lane reads it from lane 0
+      uint64_t got = 0;
+      if ((threadIdx.x & 63) == 0) got = atomicAdd((unsigned long long*)(counters + x), 1ull);
+      const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)got);
+      const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+      k = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+    } else {
+      int64_t* slot = FL::unit(lds);
+      if (threadIdx.x == 0) *slot = (int64_t)atomicAdd((unsigned long long*)(counters + x), 1ull);
+      __syncthreads();
+      k = *slot;
+      __syncthreads();
+    }
+    if (k >= len) {
+      if (++visited == kXcds) break;
+      x = (x + 1) % kXcds;
+      first = x * per + (x < rem ? x : rem);
+      len = per + (x < rem ? 1 : 0);
+      continue;
+    }
     const int64_t unit = first + k;
     // matrix b with unit_prefix[b] <= unit < unit_prefix[b + 1]
     int64_t lo = 0, hi = count - 1;
@@ -129,7 +158,7 @@ pairs_persistent_kernel(const MatDesc* __restrict__ descs, int64_t count, int64_
     }
     int64_t yq, xq;
     band_tile(descs[lo].w, unit - unit_prefix[lo], yq, xq);
-    tile_pairs<K, G>(descs[lo], yq, xq, lds, red);
+    tile_pairs<K, G>(descs[lo], yq, xq, lds, red, worker, workers);
   }
 }
 
@@ -253,7 +282,7 @@ hipError_t launch_tiles_t(const MatDesc& d, hipStream_t s) {
 
 template <int K, int G>
 hipError_t launch_jobs_t(const MatDesc& d, hipStream_t s) {
-  constexpr int kGroups = kBlock / G;
+  constexpr int kGroups = FastLds<K, G>::kGroups;
   int64_t count = d.J_end - d.J_begin;
   int64_t grid = (count + kGroups - 1) / kGroups;
   if (grid > kMaxPairGrid) grid = kMaxPairGrid;

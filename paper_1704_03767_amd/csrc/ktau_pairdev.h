@@ -248,13 +248,31 @@ struct TieWalk {
   }
 };
 
+// Waves per SIMD that the register allocation of a fast-path kernel must
+// allow (the second launch bound; the VGPR file holds 512 per lane): keys and
+// gather indices take K VGPRs, so K = 64 is held to four waves, smaller K to
+// five.
+template <int K, int G>
+constexpr int fast_waves() {
+  return K >= 64 ? 4 : 5;
+}
+
 // LDS words per group: the v rank row (uint16), reused for v' on the tie
-// path, plus the network's exchange buffer for 256-lane groups.
+// path, plus the network's exchange buffer for 256-lane groups.  A
+// workgroup's LDS is exactly its groups' words (so that, e.g., 16 groups of
+// 1024 keys take 32 KB and five workgroups fit a CU), then for 256-lane groups
+// the cross-wave reduction words and a 64-bit work-unit slot.
 template <int K, int G>
 struct FastLds {
   static constexpr int kRowWords = K * G / 2;
   static constexpr int kXWords = G == 256 ? (K / 2) * 256 : 0;
-  static constexpr int kWords = kRowWords + kXWords + 16;
+  static constexpr int kWords = kRowWords + kXWords;
+  static constexpr int kGroups = kBlock / G;
+  static constexpr int kBlockWords = kGroups * kWords + (G == 256 ? 8 : 0);
+  static __device__ __forceinline__ uint32_t* red(uint32_t* lds) { return lds + kGroups * kWords; }
+  static __device__ __forceinline__ int64_t* unit(uint32_t* lds) {
+    return (int64_t*)(lds + kGroups * kWords + 4);
+  }
 };
 
 // n_d and n3 of rows (y, x) unless both rows exceed the tie budget (then

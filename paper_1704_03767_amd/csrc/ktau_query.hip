@@ -21,10 +21,11 @@ namespace {
 // ------------------------------------------------------------ pair kernels
 
 template <int K, int G>
-__global__ void __launch_bounds__(kBlock) query_pairs_kernel(QueryDesc qd) {
-  constexpr int kGroups = kBlock / G;
-  __shared__ uint32_t lds[kGroups * FastLds<K, G>::kWords];
-  __shared__ uint32_t red[kWavesPerBlock];
+__global__ void __launch_bounds__(kBlock, (fast_waves<K, G>())) query_pairs_kernel(QueryDesc qd) {
+  using FL = FastLds<K, G>;
+  constexpr int kGroups = FL::kGroups;
+  __shared__ uint32_t lds[FL::kBlockWords];
+  uint32_t* red = FL::red(lds);
   if (*qd.status != 0) return;
   const int group = threadIdx.x / G;
   const int lane = threadIdx.x % G;
