@@ -84,7 +84,7 @@ int prepass_ws(const float* X, int64_t m, int64_t n, void* ws, int64_t* n1_out, 
   if (launch_prepass(X, m, n, (uint16_t*)(base + L.perm), (uint16_t*)(base + L.rank),
                      (uint16_t*)(base + L.rstart), L.ld, (int64_t*)(base + L.n1), n1_out,
                      (int32_t*)(base + L.nruns), (uint64_t*)(base + L.runs),
-                     status ? status : (int32_t*)base,
+                     status ? status : (int32_t*)base, true,
                      s) != hipSuccess)
     return KTAU_EDEVICE;
   return KTAU_OK;
@@ -168,7 +168,7 @@ int ktau_rank(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* ra
   if (!X || !status || m < 1 || n < 1 || m > (int64_t)0x7fffffff) return KTAU_EINVAL;
   if (n > KTAU_MAX_N) return KTAU_ERANGE;
   const hipError_t e = launch_prepass(X, m, n, perm, rank, rstart, n, nullptr, n1, nullptr,
-                                      nullptr, status, (hipStream_t)stream);
+                                      nullptr, status, false, (hipStream_t)stream);
   return e == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
 }
 

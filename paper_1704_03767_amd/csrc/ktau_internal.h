@@ -63,8 +63,8 @@ __host__ __device__ inline void tile_coord(int64_t w, int64_t t, int64_t& yq, in
 // ---- device views
 
 struct RankView {
-  const uint16_t* perm;     // [rows][ld] sorted position -> sample
-  const uint16_t* rank;     // [rows][ld] sample -> dense rank
+  const uint16_t* perm;     // [rows][ld] sorted position -> 2 x sample (byte offset in a rank row)
+  const uint16_t* rank;     // [rows][ld] sample -> 2 x dense rank
   const uint16_t* rstart;   // [rows][ld] sorted position -> first position of its tie run
   const int64_t* n1;        // [rows]
   const int32_t* nruns;     // [rows] number of tie runs of length >= 2
@@ -165,7 +165,8 @@ struct MatDesc {
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* nruns, uint64_t* runs, int32_t* status, hipStream_t s);
+                          int32_t* nruns, uint64_t* runs, int32_t* status, bool doubled,
+                          hipStream_t s);
 
 // Rank pre-pass of every row of every matrix of a descriptor table.
 hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t total_rows,

@@ -38,8 +38,19 @@ __device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t yq, int64_t
   const int q = d.q;
   const int64_t budget = direct_budget(d.n);
   Deferred<G> done;
-  for (int p = worker; p < q * q; p += workers) {
-    const int64_t y = yq * q + p / q, x = xq * q + p % q;
+  // pair p of the tile is (row p / q, column p % q); (py, px) follow p
+  int py = worker / q, px = worker % q;
+  const int step_y = workers / q, step_x = workers % q;
+  auto next = [&]() {
+    py += step_y;
+    px += step_x;
+    if (px >= q) {
+      px -= q;
+      ++py;
+    }
+  };
+  for (int p = worker; p < q * q; p += workers, next()) {
+    const int64_t y = yq * q + py, x = xq * q + px;
     if (y >= x || x >= d.m) continue;
     uint32_t nd, n3;
     if (!pair_fast<K, G>(d.rv, y, d.rv, x, d.n, budget, lds, red, lane, nd, n3)) continue;

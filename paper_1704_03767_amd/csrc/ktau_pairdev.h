@@ -308,27 +308,36 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
     load_words<K>(rv_v.rank + v * ld + k0, w);
     store_words<K>(row + k0, w);
   }
+  // workspace perm entries are byte offsets into a rank row (2 x sample)
   uint32_t pw[KV];
   if (in_row) {
     load_words<K>(ru_v.perm + u * ld + k0, pw);
   } else {
+    // a lane wholly past the row: its own slots of the LDS row get the
+    // padding key and it gathers them
+    uint32_t w[KV];
 #pragma unroll
-    for (int i = 0; i < KV; ++i) pw[i] = 0;
+    for (int i = 0; i < KV; ++i) {
+      w[i] = 0xFFFEFFFEu;
+      pw[i] = (uint32_t)(2 * (k0 + 2 * i)) | ((uint32_t)(2 * (k0 + 2 * i + 1)) << 16);
+    }
+    store_words<K>(row + k0, w);
   }
   group_sync<G>();
-  // v'[k] = rank_v[perm_u[k]], packed: VGPR j holds k0 + j and k0 + j + KV;
-  // keys are 2 v' (the network's tag goes in bit 0).  Row tails past n hold
-  // perm[k] = k and rank 0x7FFF, so they gather the padding key 0xFFFE; lanes
-  // wholly past the row get it directly.
+  // v'[k] = rank_v[perm_u[k]], packed: VGPR j holds k0 + j and k0 + j + KV.
+  // Workspace ranks are stored doubled, so the gathered values are already
+  // the network's keys 2 v' (its tag goes in bit 0); row tails past n hold
+  // perm[k] = 2k and 0xFFFE, the padding key.
+  const char* rowb = (const char*)row;
   u16x2 key[KV];
 #pragma unroll
   for (int j = 0; j < KV; ++j) {
     const uint32_t a = j % 2 ? pw[j / 2] >> 16 : pw[j / 2] & 0xFFFFu;
     const uint32_t b = (j + KV) % 2 ? pw[(j + KV) / 2] >> 16 : pw[(j + KV) / 2] & 0xFFFFu;
     u16x2 t;
-    t.x = row[a];
-    t.y = row[b];
-    key[j] = in_row ? (u16x2)(t << (unsigned short)1) : bitonic::vec(0xFFFEFFFEu);
+    t.x = *(const uint16_t*)(rowb + a);
+    t.y = *(const uint16_t*)(rowb + b);
+    key[j] = t;
   }
   uint32_t xin = 0, tie = 0;
   if (n1u != 0) {
@@ -492,7 +501,7 @@ __device__ void pair_composite(const RankView& ry, int64_t y, const RankView& rx
 #pragma unroll
   for (int r = 0; r < K; ++r) {
     const int k = k0 + r;
-    key[r] = k < n ? ((uint32_t)ru[k] << 16) | (uint32_t)rk[pu[k]] : kPadKey;
+    key[r] = k < n ? ((uint32_t)ru[k] << 16) | (uint32_t)rk[pu[k] >> 1] : kPadKey;
   }
   (void)sort_count<K, G>(key, buf, lane, red);
   // joint ties: in the (u, v)-sorted sequence, sum over positions of the

@@ -8,7 +8,10 @@
 //
 // One 256-thread workgroup per row.  The row's (value key, sample) pairs are
 // bitonic-sorted in LDS as 64-bit words (order-preserving 32-bit key << 16 |
-// sample), then block scans produce dense ranks and run starts.
+// sample), then block scans produce dense ranks and run starts.  Into a pair
+// workspace the sample indices and ranks are written doubled (byte offsets
+// into a rank row, and ranks with a free low bit for the pair network's
+// tag); the rank entry point writes them plain.
 #include "ktau_internal.h"
 
 namespace ktau {
@@ -75,7 +78,7 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
                             uint16_t* __restrict__ rstart, int64_t ld,
                             int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
                             int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
-                            int32_t* __restrict__ status, uint64_t* s_keys) {
+                            int32_t* __restrict__ status, uint64_t* s_keys, int dbl) {
   __shared__ int s_scan[kThreads / 64];
   __shared__ unsigned long long s_n1;
   const float* x = X + row * (int64_t)n;
@@ -146,25 +149,26 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
         ++r;
         st = k;
       }
-      if (prow) prow[k] = (uint16_t)sample;
-      if (rrow) rrow[sample] = (uint16_t)r;
+      if (prow) prow[k] = (uint16_t)(sample << dbl);
+      if (rrow) rrow[sample] = (uint16_t)(r << dbl);
       if (srow) srow[k] = (uint16_t)st;
       ties += (unsigned long long)(k - st);
     } else if (k < ld) {
-      if (prow) prow[k] = (uint16_t)k;
+      if (prow) prow[k] = (uint16_t)(k << dbl);
       if (srow) srow[k] = (uint16_t)k;
     }
   }
   // Padding of rows longer than the sort width (ld > npow2 never happens for
   // the workspace layout, but callers may pass a wider ld).
   for (int k = npow2 + tid; k < ld; k += kThreads) {
-    if (prow) prow[k] = (uint16_t)k;
+    if (prow) prow[k] = (uint16_t)(k << dbl);
     if (srow) srow[k] = (uint16_t)k;
   }
-  // Tail positions n..ld-1 map to themselves and rank 0x7FFF, above every
-  // real rank, so the pair kernels gather padding keys without a bounds test.
+  // Tail positions n..ld-1 map to themselves and rank 0x7FFF (doubled in a
+  // workspace), above every real rank, so the pair kernels gather padding
+  // keys without a bounds test.
   if (rrow)
-    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)0x7FFF;
+    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)(0x7FFF << dbl);
   atomicAdd(&s_n1, ties);
   __syncthreads();
   if (tid == 0) {
@@ -209,12 +213,12 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
                uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
                int64_t* __restrict__ n1_out, int32_t* __restrict__ nruns,
-               uint64_t* __restrict__ runs, int32_t* __restrict__ status) {
+               uint64_t* __restrict__ runs, int32_t* __restrict__ status, int dbl) {
   extern __shared__ uint64_t s_keys[];
   const int64_t row = blockIdx.x;
   if (row >= m) return;
   prepass_row(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
-              s_keys);
+              s_keys, dbl);
 }
 
 // Every row of every matrix of a batch: block b ranks global row b, found by
@@ -236,7 +240,7 @@ prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
   while (npow2 < d.n) npow2 <<= 1;
   prepass_row(d.X, row, d.n, npow2, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
               (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
-              (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, s_keys);
+              (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, s_keys, 1);
 }
 
 }  // namespace
@@ -253,12 +257,14 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* nruns, uint64_t* runs, int32_t* status, hipStream_t s) {
+                          int32_t* nruns, uint64_t* runs, int32_t* status, bool doubled,
+                          hipStream_t s) {
   int npow2 = 64;
   while (npow2 < n) npow2 <<= 1;
   size_t lds = (size_t)npow2 * sizeof(uint64_t);
   hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)m), dim3(kThreads), lds, s, X, m, (int)n,
-                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status);
+                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+                     doubled ? 1 : 0);
   return hipGetLastError();
 }
 
