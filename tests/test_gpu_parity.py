@@ -244,3 +244,25 @@ def test_medium_workload_sampled():
 @pytest.mark.slow
 def test_gene_expression_scale_sampled():
     _sampled(3, 20000, 33)
+
+
+@pytest.mark.slow
+def test_gene_expression_scale_batched_equals_plain():
+    # the launch configuration bench.py reports as its value: a one-matrix
+    # batched plan (autotuned scheme, persistent kernel, hipGraph), replayed
+    # twice; every output equals the plain call's (itself checked against the
+    # oracle on samples above)
+    X = synth.config_matrix(3)
+    Xd = torch.from_numpy(X).cuda()
+    plain = K.ktau_allpairs(Xd)
+    b = K.KtauBatch([Xd])
+    for _ in range(2):
+        b.run()
+        assert b.status() == K.KTAU_OK
+        got = b.outs[0]
+        for k in ("nc", "nd", "n3", "n1"):
+            assert torch.equal(got[k], plain[k]), k
+        assert torch.equal(got["tau_b"].isnan(), plain["tau_b"].isnan())
+        ok = ~plain["tau_b"].isnan()
+        assert torch.equal(got["tau_b"][ok], plain["tau_b"][ok])
+    b.close()

@@ -199,3 +199,15 @@ def test_server_rejects_nan_and_bad_k():
     assert e.value.status == K.KTAU_ERANGE
     srv.close()
     kdb.close()
+
+
+@pytest.mark.slow
+def test_query_full_size_database():
+    # the serving workload's database (20000 x 800) and k = 100, against the
+    # oracle's full sort for a few queries
+    db = synth.database(20000, 800, 5)
+    Q = synth.queries(db, 4, 61)
+    kdb = S.KtauDb(torch.from_numpy(db.X).cuda())
+    got = {a: b.cpu().numpy() for a, b in S.ktau_query(kdb, torch.from_numpy(Q).cuda(), 100).items()}
+    _check_topk(got, oracle.query_topk(db.X, Q, 100))
+    kdb.close()
