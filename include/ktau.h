@@ -57,7 +57,7 @@ extern "C" {
 #define KTAU_ETIMEDOUT -8 /* server: wait timed out                             */
 
 /* Largest sample count n supported by the rank pre-pass and pair kernels. */
-#define KTAU_MAX_N 4096
+#define KTAU_MAX_N 16384
 
 /* Human-readable name of a status code (static storage). */
 const char* ktau_status_string(int status);

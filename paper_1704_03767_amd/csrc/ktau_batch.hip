@@ -236,7 +236,7 @@ int enqueue_batch(ktau_batch* b, hipStream_t s) {
     if (launch_pairs_persistent(c.scheme, b->descs + c.first, c.count, c.total_units, c.prefix,
                                 c.counters, b->words, s) != hipSuccess)
       return KTAU_EDEVICE;
-  if (launch_tie_passes_batch(b->descs, b->count, s) != hipSuccess) return KTAU_EDEVICE;
+  if (launch_tie_passes_batch(b->descs, b->count, b->max_n, s) != hipSuccess) return KTAU_EDEVICE;
   return KTAU_OK;
 }
 

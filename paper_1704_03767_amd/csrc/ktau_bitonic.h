@@ -64,6 +64,9 @@ struct Net {
   static constexpr int LOGG = ilog2(G);
   static constexpr int LOGN = LOGK + LOGG;
   static constexpr int N = K * G;
+  // VGPRs exchanged per LDS round across the waves of a 256-lane group (the
+  // exchange buffer holds kXChunk * G words)
+  static constexpr int kXChunk = KV < 16 ? KV : 16;
   static_assert(K >= 2 && K <= 64 && (K & (K - 1)) == 0, "K is a power of two <= 64");
   static_assert(G == 8 || G == 16 || G == 32 || G == 64 || G == 256,
                 "part of a wave, a wave or a 256-lane workgroup");
@@ -177,18 +180,22 @@ struct Net {
           v[0] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
         }
       } else {
-        // across the waves of a 256-lane group, through LDS
+        // across the waves of a 256-lane group, through LDS, kXChunk VGPRs
+        // at a time
         const uint32_t keep_min = lane_mask(lane, lb);
 #pragma unroll
-        for (int j = 0; j < KV; ++j) xbuf[j * G + plane] = bits(v[j]);
-        __syncthreads();
+        for (int j0 = 0; j0 < KV; j0 += kXChunk) {
 #pragma unroll
-        for (int j = 0; j < KV; ++j) {
-          const u16x2 p = vec(xbuf[j * G + (plane ^ (1 << pb))]);
-          const u16x2 mn = pmin(v[j], p), mx = pmax(v[j], p);
-          v[j] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
+          for (int j = 0; j < kXChunk; ++j) xbuf[j * G + plane] = bits(v[j0 + j]);
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < kXChunk; ++j) {
+            const u16x2 p = vec(xbuf[j * G + (plane ^ (1 << pb))]);
+            const u16x2 mn = pmin(v[j0 + j], p), mx = pmax(v[j0 + j], p);
+            v[j0 + j] = vec((bits(mn) & keep_min) | (bits(mx) & ~keep_min));
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
     }
   }

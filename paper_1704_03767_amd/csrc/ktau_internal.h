@@ -103,7 +103,9 @@ struct PairOut {
   X(kWaveK32, 32, 64)           \
   X(kWaveK64, 64, 64)           \
   X(kSub8K32, 32, 8)            \
-  X(kSub8K64, 64, 8)
+  X(kSub8K64, 64, 8)            \
+  X(kBlockK32, 32, 256)         \
+  X(kBlockK64, 64, 256)
 
 enum Scheme : int32_t {
 #define KTAU_ENUM(S, K, G) S,
@@ -184,7 +186,8 @@ hipError_t launch_pairs_persistent(int scheme, const MatDesc* descs_dev, int64_t
                                    int64_t* counters_dev, const int32_t* status, hipStream_t s);
 
 // Heavy-row lists and the composite pass for every matrix of a table.
-hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, hipStream_t s);
+hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, int max_n,
+                                   hipStream_t s);
 
 // ---- host helpers shared by the API units (ktau_api.hip)
 

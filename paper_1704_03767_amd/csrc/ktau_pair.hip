@@ -236,38 +236,35 @@ __device__ void composite_matrix(const MatDesc& d, uint32_t* lds_all, uint32_t* 
   }
 }
 
-constexpr int kCompLdsWords = CompLds<16, 256>::kWords > 4 * CompLds<16, 64>::kWords
-                                  ? CompLds<16, 256>::kWords
-                                  : 4 * CompLds<16, 64>::kWords;
+// The composite pass runs on whole waves or 256-lane blocks, chosen on the
+// host by n (the largest n of a batch): (K, G) = (2, 64) for n <= 128 up to
+// (64, 256) for n <= 16384.  It is rare; the fast path's scheme does not
+// matter to it.
+#define KTAU_FOR_EACH_COMPOSITE(X) \
+  X(128, 2, 64) X(256, 4, 64) X(512, 8, 64) X(1024, 16, 64) X(2048, 8, 256) X(4096, 16, 256) \
+  X(8192, 32, 256) X(16384, 64, 256)
 
-// The composite pass runs on whole waves or 256-lane blocks, chosen by n
-// alone (it is rare; the fast path's scheme does not matter to it).
-__device__ void composite_dispatch(const MatDesc& d, uint32_t* lds, uint32_t* red) {
-  if (d.n <= 128) composite_matrix<2, 64>(d, lds, red);
-  else if (d.n <= 256) composite_matrix<4, 64>(d, lds, red);
-  else if (d.n <= 512) composite_matrix<8, 64>(d, lds, red);
-  else if (d.n <= 1024) composite_matrix<16, 64>(d, lds, red);
-  else if (d.n <= 2048) composite_matrix<8, 256>(d, lds, red);
-  else composite_matrix<16, 256>(d, lds, red);
-}
-
+template <int K, int G>
 __global__ void __launch_bounds__(kBlock) composite_plain_kernel(MatDesc d) {
-  __shared__ uint32_t lds[kCompLdsWords];
+  constexpr int kGroups = kBlock / G;
+  __shared__ uint32_t lds[kGroups * CompLds<K, G>::kWords];
   __shared__ uint32_t red[kWavesPerBlock];
   if (*d.status != 0) return;
   if (*d.heavy_count < 2) return;
-  composite_dispatch(d, lds, red);
+  composite_matrix<K, G>(d, lds, red);
 }
 
+template <int K, int G>
 __global__ void __launch_bounds__(kBlock) composite_batch_kernel(const MatDesc* descs,
                                                                  int64_t count) {
-  __shared__ uint32_t lds[kCompLdsWords];
+  constexpr int kGroups = kBlock / G;
+  __shared__ uint32_t lds[kGroups * CompLds<K, G>::kWords];
   __shared__ uint32_t red[kWavesPerBlock];
   for (int64_t b = 0; b < count; ++b) {
     const MatDesc d = descs[b];
     if (*d.status != 0) continue;
     if (*d.heavy_count < 2) continue;
-    composite_dispatch(d, lds, red);
+    composite_matrix<K, G>(d, lds, red);
   }
 }
 
@@ -308,7 +305,7 @@ const char* scheme_name(int s) {
   static const char* names[] = {"wave_k2",   "wave_k4",   "wave_k8",   "wave_k16",  "block_k4",
                                 "block_k8",  "block_k16", "sub8_k16",  "sub16_k16", "sub16_k32",
                                 "sub16_k64", "sub32_k32", "sub32_k64", "wave_k32",  "wave_k64",
-                                "sub8_k32",  "sub8_k64"};
+                                "sub8_k32",  "sub8_k64",  "block_k32", "block_k64"};
   static_assert(sizeof(names) / sizeof(names[0]) == kNumSchemes, "one name per scheme");
   return (s >= 0 && s < kNumSchemes) ? names[s] : "invalid";
 }
@@ -321,7 +318,9 @@ int default_scheme(int64_t n) {
   if (n <= 512) return kSub16K32;
   if (n <= 1024) return kSub32K32;
   if (n <= 2048) return kWaveK32;
-  return kWaveK64;
+  if (n <= 4096) return kWaveK64;
+  if (n <= 8192) return kBlockK32;
+  return kBlockK64;
 }
 
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
@@ -337,8 +336,15 @@ hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
   // heavy rows, then the composite pass over their pairs
   hipLaunchKernelGGL(heavy_plain_kernel, dim3(1), dim3(kBlock), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(composite_plain_kernel, dim3((unsigned)device_cus()), dim3(kBlock), 0, s, d);
-  return hipGetLastError();
+#define KTAU_COMP(N, K, G)                                                                    \
+  if (d.n <= N) {                                                                             \
+    hipLaunchKernelGGL((composite_plain_kernel<K, G>), dim3((unsigned)device_cus()),           \
+                       dim3(kBlock), 0, s, d);                                                 \
+    return hipGetLastError();                                                                 \
+  }
+  KTAU_FOR_EACH_COMPOSITE(KTAU_COMP)
+#undef KTAU_COMP
+  return hipErrorInvalidValue;
 }
 
 template <int K, int G>
@@ -379,13 +385,20 @@ hipError_t launch_heavy(const MatDesc& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, hipStream_t s) {
+hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, int max_n,
+                                   hipStream_t s) {
   hipLaunchKernelGGL(heavy_batch_kernel, dim3((unsigned)count), dim3(kBlock), 0, s, descs_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(composite_batch_kernel, dim3((unsigned)device_cus()), dim3(kBlock), 0, s,
-                     descs_dev, count);
-  return hipGetLastError();
+#define KTAU_COMP(N, K, G)                                                                    \
+  if (max_n <= N) {                                                                           \
+    hipLaunchKernelGGL((composite_batch_kernel<K, G>), dim3((unsigned)device_cus()),           \
+                       dim3(kBlock), 0, s, descs_dev, count);                                  \
+    return hipGetLastError();                                                                 \
+  }
+  KTAU_FOR_EACH_COMPOSITE(KTAU_COMP)
+#undef KTAU_COMP
+  return hipErrorInvalidValue;
 }
 
 }  // namespace ktau

@@ -265,7 +265,7 @@ constexpr int fast_waves() {
 template <int K, int G>
 struct FastLds {
   static constexpr int kRowWords = K * G / 2;
-  static constexpr int kXWords = G == 256 ? (K / 2) * 256 : 0;
+  static constexpr int kXWords = G == 256 ? bitonic::Net<K, G>::kXChunk * 256 : 0;
   static constexpr int kWords = kRowWords + kXWords;
   static constexpr int kGroups = kBlock / G;
   static constexpr int kBlockWords = kGroups * kWords + (G == 256 ? 8 : 0);

@@ -243,6 +243,15 @@ prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
               (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, s_keys, 1);
 }
 
+// Rows longer than 8192 samples sort 128 KB of keys, above the 64 KB of
+// dynamic LDS a launch gets by default; raise the kernel's limit once.
+template <typename F>
+hipError_t allow_lds(F kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 }  // namespace
 
 hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t total_rows,
@@ -250,6 +259,8 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
   int npow2 = 64;
   while (npow2 < max_n) npow2 <<= 1;
   const size_t lds = (size_t)npow2 * sizeof(uint64_t);
+  hipError_t e = allow_lds(prepass_batch_kernel, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prepass_batch_kernel, dim3((unsigned)total_rows), dim3(kThreads), lds, s,
                      descs_dev, count, row_prefix_dev);
   return hipGetLastError();
@@ -261,7 +272,9 @@ hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, 
                           hipStream_t s) {
   int npow2 = 64;
   while (npow2 < n) npow2 <<= 1;
-  size_t lds = (size_t)npow2 * sizeof(uint64_t);
+  const size_t lds = (size_t)npow2 * sizeof(uint64_t);
+  hipError_t e = allow_lds(prepass_kernel, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)m), dim3(kThreads), lds, s, X, m, (int)n,
                      npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
                      doubled ? 1 : 0);

@@ -185,7 +185,9 @@ hipError_t query_composite(const QueryDesc& qd, hipStream_t s) {
   else if (qd.n <= 512) KTAU_COMP(8, 64);
   else if (qd.n <= 1024) KTAU_COMP(16, 64);
   else if (qd.n <= 2048) KTAU_COMP(8, 256);
-  else KTAU_COMP(16, 256);
+  else if (qd.n <= 4096) KTAU_COMP(16, 256);
+  else if (qd.n <= 8192) KTAU_COMP(32, 256);
+  else KTAU_COMP(64, 256);
 #undef KTAU_COMP
   return hipGetLastError();
 }

@@ -25,7 +25,7 @@ KTAU_EBUSY = -5
 KTAU_ENAN = -6
 KTAU_ECANCELED = -7
 KTAU_ETIMEDOUT = -8
-KTAU_MAX_N = 4096
+KTAU_MAX_N = 16384
 
 _lock = threading.Lock()
 _lib = None

@@ -75,7 +75,7 @@ def test_scheme_table():
     assert len(names) == K.lib().ktau_scheme_count()
     caps = [K.ktau_scheme_capacity(i) for i in range(len(names))]
     assert max(caps) >= K.KTAU_MAX_N
-    for n in (2, 64, 128, 129, 512, 1024, 1025, 4096):
+    for n in (2, 64, 128, 129, 512, 1024, 1025, 4096, 4097, 8192, 8193, 16384):
         s = K.ktau_default_scheme(n)
         assert caps[s] >= n
     assert K.ktau_scheme_capacity(-1) == -1

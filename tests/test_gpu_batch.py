@@ -46,6 +46,27 @@ def test_batch_matches_oracle_and_plain(use_graph, tmp_path):
     b.close()
 
 
+def test_batch_with_large_samples():
+    # classes of 256-lane schemes next to small ones; the pre-pass and the
+    # composite pass are sized by the largest n of the batch
+    shapes = [(21, 16384), (3, 9000), (40, 300), (2, 8192), (17, 4097)]
+    mats = [synth.batch_matrix(s, 47, i) for i, s in enumerate(shapes)]
+    mats[1][1] = np.floor(mats[1][1])                 # a heavily tied row
+    mats[1][2] = np.round(mats[1][2])
+    dev = [torch.from_numpy(X).cuda() for X in mats]
+    b = K.KtauBatch(dev)
+    for _ in range(2):
+        b.run()
+        assert b.status() == K.KTAU_OK
+        for i, X in enumerate(mats):
+            got = _np(b.outs[i])
+            want = oracle.allpairs(X, "gse")
+            for k in ("nc", "nd", "n3", "n1"):
+                assert np.array_equal(got[k], want[k]), (i, k, X.shape, b.plan(i))
+            assert np.array_equal(got["tau_b"], want["tau_b"], equal_nan=True), i
+    b.close()
+
+
 def test_batch_forced_schemes():
     mats = _small_batch(10, 43)
     dev = [torch.from_numpy(X).cuda() for X in mats]

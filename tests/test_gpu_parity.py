@@ -68,6 +68,7 @@ def _oracle_rstart(order, rank):
 
 
 @pytest.mark.parametrize("shape_seed", [(64, 128, 1), (33, 1000, 2), (17, 4096, 3), (5, 2, 4),
+                                        (6, 8193, 6), (5, 16384, 7),
                                         (9, 65, 5)])
 def test_prepass_matches_oracle(shape_seed):
     m, n, seed = shape_seed
@@ -151,6 +152,42 @@ def test_block_schemes_on_edges(n):
     for scheme in ALL_SCHEMES:
         if K.ktau_scheme_capacity(scheme) >= n:
             _check_full(X, scheme=scheme)
+
+
+# Samples beyond 4096 run on 256-lane blocks with 32 or 64 keys per lane.
+LARGE_N = [4097, 5000, 8191, 8192, 8193, 12289, 16383, 16384]
+
+
+@pytest.mark.parametrize("n", LARGE_N)
+def test_large_sample_counts(n):
+    m = 9
+    X = _edge_matrix(m, n, 1000 + n)
+    got = _check_full(X)
+    assert got["tau_b"][K.ktau_pair_to_job(m, 2, 4)] == 1.0
+    assert got["tau_b"][K.ktau_pair_to_job(m, 2, 3)] == -1.0
+    for scheme in ALL_SCHEMES:
+        if K.ktau_scheme_capacity(scheme) >= n:
+            _check_full(X, scheme=scheme, q=2)
+
+
+@pytest.mark.parametrize("n", [6000, 16384])
+def test_large_gene_expression_tiles(n):
+    # several tiles and a ragged tail of rows, rows with 2% exact zeros
+    X = synth.lognormal_blocks(37, n, 60 + n % 7)
+    _check_full(X)
+    _check_full(X, q=5)
+
+
+def test_large_heavy_tie_paths():
+    rng = np.random.default_rng(23)
+    for n in (5000, 16384):
+        rows = [rng.integers(0, lv, n).astype(np.float32) for lv in (2, 3, 8, 200, 3000)]
+        rows.append(np.where(rng.random(n) < 0.9, 0.0, rng.standard_normal(n)).astype(np.float32))
+        rows.append(rng.standard_normal(n).astype(np.float32))
+        X = np.stack(rows)
+        for scheme in ALL_SCHEMES:
+            if K.ktau_scheme_capacity(scheme) >= n:
+                _check_full(X, scheme=scheme)
 
 
 @pytest.mark.parametrize("m", [2, 3, 7, 8, 9, 17])

@@ -71,6 +71,16 @@ def test_query_every_scheme(monkeypatch):
         kdb.close()
 
 
+@pytest.mark.parametrize("n", [8192, 16384])
+def test_query_large_samples(n):
+    db = _db(m=120, n=n, seed=58)
+    Q = _queries(db, 3, 59)
+    kdb = S.KtauDb(torch.from_numpy(db.X).cuda())
+    got = {a: b.cpu().numpy() for a, b in S.ktau_query(kdb, torch.from_numpy(Q).cuda(), 30).items()}
+    _check_topk(got, oracle.query_topk(db.X, Q, 30))
+    kdb.close()
+
+
 def test_query_pads_when_k_exceeds_rows():
     db = _db(m=40, n=300, seed=53)
     Q = _queries(db, 3, 54)
