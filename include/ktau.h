@@ -56,8 +56,10 @@ extern "C" {
 #define KTAU_ECANCELED -7 /* server: request cancelled or failed in its slot    */
 #define KTAU_ETIMEDOUT -8 /* server: wait timed out                             */
 
-/* Largest sample count n supported by the rank pre-pass and pair kernels. */
-#define KTAU_MAX_N 16384
+/* Largest sample count n.  Ranks are 16-bit and the pair kernels key every
+ * sample by twice its rank in 16 bits (the spare bit carries the sort
+ * network's tag), which bounds n by 2^15. */
+#define KTAU_MAX_N 32768
 
 /* Human-readable name of a status code (static storage). */
 const char* ktau_status_string(int status);
@@ -91,10 +93,17 @@ int ktau_tile_to_coord(int64_t w, int64_t t, int64_t* yq_host, int64_t* xq_host)
  *                         position k, uint16;
  *   n1_dev[r]           = sum over tie runs of t(t-1)/2, int64.
  * Any output may be NULL.  status_dev (int32, device) receives KTAU_ENAN if a
- * NaN is present (written only on error; the caller clears it). */
+ * NaN is present (written only on error; the caller clears it).
+ * ws_dev: device scratch of at least ktau_rank_workspace_size(m, n) bytes,
+ * 256-byte aligned, owned by the caller and free again when the stream has
+ * passed the call; rows longer than 16384 finish their sort there.  It may be
+ * NULL when that size is 0 (n <= 16384).  Errors: KTAU_EINVAL (null X or
+ * status, m or n < 1, missing or misaligned scratch), KTAU_ERANGE
+ * (n > KTAU_MAX_N), KTAU_ENOMEM (ws_bytes too small). */
+size_t ktau_rank_workspace_size(int64_t m, int64_t n);
 int ktau_rank(const float* X_dev, int64_t m, int64_t n, uint16_t* perm_dev,
               uint16_t* rank_dev, uint16_t* rstart_dev, int64_t* n1_dev,
-              int32_t* status_dev, void* stream);
+              int32_t* status_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Plain all-pairs.

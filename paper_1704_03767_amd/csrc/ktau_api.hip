@@ -15,7 +15,7 @@ __global__ void clear_words_kernel(int32_t* p, int count) {
 
 WsLayout ws_layout(int64_t m, int64_t n) {
   WsLayout L;
-  L.ld = round_up(n, kRowAlign);
+  L.ld = row_ld(n);
   const int64_t rowbytes = m * L.ld * (int64_t)sizeof(uint16_t);
   int64_t off = (int64_t)kWsHeader;
   L.perm = (size_t)off;
@@ -32,6 +32,8 @@ WsLayout ws_layout(int64_t m, int64_t n) {
   off = round_up(off + m * (L.ld / 2) * (int64_t)sizeof(uint64_t), (int64_t)kAlign);
   L.heavy = (size_t)off;
   off = round_up(off + m * (int64_t)sizeof(int32_t), (int64_t)kAlign);
+  L.sort = (size_t)off;
+  off = round_up(off + (int64_t)sort_scratch_bytes(m, n), (int64_t)kAlign);
   L.total = (size_t)off;
   return L;
 }
@@ -65,6 +67,7 @@ MatDesc matdesc(void* ws, int64_t m, int64_t n, const ktau_pair_out& out, int sc
   d.status = status ? status : (const int32_t*)base;
   d.heavy_count = (int32_t*)(base + 4);
   d.heavy = (int32_t*)(base + L.heavy);
+  d.sort_tmp = (uint64_t*)(base + L.sort);
   d.m = m;
   d.n = (int32_t)n;
   d.scheme = scheme;
@@ -84,7 +87,7 @@ int prepass_ws(const float* X, int64_t m, int64_t n, void* ws, int64_t* n1_out, 
   if (launch_prepass(X, m, n, (uint16_t*)(base + L.perm), (uint16_t*)(base + L.rank),
                      (uint16_t*)(base + L.rstart), L.ld, (int64_t*)(base + L.n1), n1_out,
                      (int32_t*)(base + L.nruns), (uint64_t*)(base + L.runs),
-                     status ? status : (int32_t*)base, true,
+                     status ? status : (int32_t*)base, true, (uint64_t*)(base + L.sort),
                      s) != hipSuccess)
     return KTAU_EDEVICE;
   return KTAU_OK;
@@ -163,12 +166,21 @@ int ktau_tile_to_coord(int64_t w, int64_t t, int64_t* yq, int64_t* xq) {
   return KTAU_OK;
 }
 
+size_t ktau_rank_workspace_size(int64_t m, int64_t n) {
+  if (m < 1 || n < 1 || n > KTAU_MAX_N) return 0;
+  return sort_scratch_bytes(m, n);
+}
+
 int ktau_rank(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
-              uint16_t* rstart, int64_t* n1, int32_t* status, void* stream) {
+              uint16_t* rstart, int64_t* n1, int32_t* status, void* ws, size_t ws_bytes,
+              void* stream) {
   if (!X || !status || m < 1 || n < 1 || m > (int64_t)0x7fffffff) return KTAU_EINVAL;
   if (n > KTAU_MAX_N) return KTAU_ERANGE;
+  const size_t need = sort_scratch_bytes(m, n);
+  if (need > 0 && (!ws || ((uintptr_t)ws) % kAlign != 0)) return KTAU_EINVAL;
+  if (ws_bytes < need) return KTAU_ENOMEM;
   const hipError_t e = launch_prepass(X, m, n, perm, rank, rstart, n, nullptr, n1, nullptr,
-                                      nullptr, status, false, (hipStream_t)stream);
+                                      nullptr, status, false, (uint64_t*)ws, (hipStream_t)stream);
   return e == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
 }
 

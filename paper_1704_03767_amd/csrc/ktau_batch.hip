@@ -229,9 +229,19 @@ namespace {
 // The whole run on stream s.
 int enqueue_batch(ktau_batch* b, hipStream_t s) {
   if (clear_words(b->words, b->clear_count, s) != KTAU_OK) return KTAU_EDEVICE;
-  if (launch_prepass_batch(b->descs, b->count, b->total_rows, b->row_prefix, b->max_n, s) !=
+  int lds_n = 0;   // the longest rows the batched pre-pass sorts in LDS
+  for (const MatDesc& d : b->host_descs)
+    if (d.n <= kLdsSortMax && d.n > lds_n) lds_n = d.n;
+  if (launch_prepass_batch(b->descs, b->count, b->total_rows, b->row_prefix, lds_n, s) !=
       hipSuccess)
     return KTAU_EDEVICE;
+  for (const MatDesc& d : b->host_descs)
+    if (d.n > kLdsSortMax &&
+        launch_prepass(d.X, d.m, d.n, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
+                       (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
+                       (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, true,
+                       d.sort_tmp, s) != hipSuccess)
+      return KTAU_EDEVICE;
   for (const ClassRun& c : b->classes)
     if (launch_pairs_persistent(c.scheme, b->descs + c.first, c.count, c.total_units, c.prefix,
                                 c.counters, b->words, s) != hipSuccess)

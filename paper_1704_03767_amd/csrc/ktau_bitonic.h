@@ -67,7 +67,11 @@ struct Net {
   // VGPRs exchanged per LDS round across the waves of a 256-lane group (the
   // exchange buffer holds kXChunk * G words)
   static constexpr int kXChunk = KV < 16 ? KV : 16;
-  static_assert(K >= 2 && K <= 64 && (K & (K - 1)) == 0, "K is a power of two <= 64");
+  static_assert(K >= 2 && K <= 128 && (K & (K - 1)) == 0, "K is a power of two <= 128");
+  // Lane-spanning levels accumulate sum(raw * r) below bit kWShift and the
+  // number of raw tags above it (sum of r < K is at most K(K-1)/2).
+  static constexpr int kWShift = K <= 64 ? 12 : 14;
+  static_assert(K * (K - 1) / 2 < (1 << kWShift), "weight field");
   static_assert(G == 8 || G == 16 || G == 32 || G == 64 || G == 256,
                 "part of a wave, a wave or a 256-lane workgroup");
 
@@ -233,9 +237,9 @@ struct Net {
   // i.e. a per-lane constant minus one dot product of the raw tag bits.
   // Blocks inside a lane: q depends on (j, half) only, so the constants and
   // weights are compile-time.  Blocks spanning lanes: q = base + r (r = index
-  // in the lane, base the lane's offset in its block); the weights r + 4096
-  // give sum raw*r (< 4096) and the number of raw tags (above bit 12) in one
-  // accumulator.
+  // in the lane, base the lane's offset in its block); the weights
+  // r + 2^kWShift give sum raw*r (below bit kWShift) and the number of raw
+  // tags (above it) in one accumulator.
   static constexpr uint32_t in_lane_weight(int L, int j) {
     const uint32_t m2s = (2u << L) - 1u;
     return ((uint32_t)j & m2s) | (((uint32_t)(j + KV) & m2s) << 16);
@@ -263,7 +267,8 @@ struct Net {
       if constexpr (L + 1 < LOGK) {
         acc_in = __builtin_amdgcn_udot2(vec(t), vec(in_lane_weight(L, j)), acc_in, false);
       } else {
-        const uint32_t w = ((uint32_t)j + 4096u) | (((uint32_t)(j + KV) + 4096u) << 16);
+        constexpr uint32_t kW = 1u << kWShift;
+        const uint32_t w = ((uint32_t)j + kW) | (((uint32_t)(j + KV) + kW) << 16);
         acc = __builtin_amdgcn_udot2(vec(t), vec(w), acc, false);
       }
       if constexpr (L + 1 < LOGN) v[j] = vec(bits(v[j]) ^ t ^ tag_const<L + 1>(lane, j));
@@ -271,7 +276,7 @@ struct Net {
     if constexpr (L + 1 >= LOGK) {
       // the lane lies inside one block of 2s: its offset and orientation
       const uint32_t base = ((uint32_t)lane & ((1u << (L + 1 - LOGK)) - 1u)) << LOGK;
-      const uint32_t raw = (acc & 4095u) + base * (acc >> 12);
+      const uint32_t raw = (acc & ((1u << kWShift) - 1u)) + base * (acc >> kWShift);
       const uint32_t desc =
           (L + 1 < LOGN) ? (uint32_t)(lane >> (L + 1 - LOGK)) & 1u : 0u;
       const uint32_t all = (uint32_t)K * base + (uint32_t)(K * (K - 1) / 2);

@@ -9,16 +9,34 @@
 
 namespace ktau {
 
-// Rows of every per-variable array are padded to a multiple of this many
-// uint16 elements, so each row starts on a 128-byte boundary.
-constexpr int64_t kRowAlign = 64;
+// Rows of every per-variable array are padded to a multiple of 128 uint16
+// elements (a 256-byte boundary), so that a pair kernel lane's block of
+// K <= 128 sorted positions is either wholly inside the padded row or wholly
+// past it.
+constexpr int64_t kRowAlign = 128;
 constexpr size_t kWsHeader = 256;       // bytes: status word + reserved
 constexpr size_t kAlign = 256;
 
+// Longest row whose 64-bit sort keys one workgroup sorts in LDS (128 KB);
+// longer rows (up to KTAU_MAX_N) finish their sort in global scratch, one
+// 2 * kLdsSortMax-word slot per workgroup of at most kSortSlots.
+constexpr int kLdsSortMax = 16384;
+constexpr int64_t kSortSlots = 256;
+
+__host__ __device__ inline int64_t row_ld(int64_t n) {
+  return (n + kRowAlign - 1) / kRowAlign * kRowAlign;
+}
+
+// Bytes of sort scratch the pre-pass of m rows of length n needs.
+inline size_t sort_scratch_bytes(int64_t m, int64_t n) {
+  if (n <= kLdsSortMax) return 0;
+  return (size_t)(m < kSortSlots ? m : kSortSlots) * 2 * kLdsSortMax * sizeof(uint64_t);
+}
+
 // Sort keys: padding slots beyond n, and the sentinel read past a run end.
-// Real keys are at most 0x0FFFFFFF (16-bit tie-run id << 16 | 16-bit rank,
-// with n <= KTAU_MAX_N), so both compare above every real key and the
-// sentinel above the padding.
+// Real keys are at most 0x7FFFFFFE (15-bit tie-run start << 16 | doubled
+// rank, with n <= 16384 on that pass), so both compare above every real key
+// and the sentinel above the padding.
 constexpr uint32_t kPadKey = 0xFFFFFFFEu;
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 
@@ -105,7 +123,8 @@ struct PairOut {
   X(kSub8K32, 32, 8)            \
   X(kSub8K64, 64, 8)            \
   X(kBlockK32, 32, 256)         \
-  X(kBlockK64, 64, 256)
+  X(kBlockK64, 64, 256)         \
+  X(kBlockK128, 128, 256)
 
 enum Scheme : int32_t {
 #define KTAU_ENUM(S, K, G) S,
@@ -136,8 +155,13 @@ int default_scheme(int64_t n);
 
 // Comparisons the direct in-run tie count may spend on one pair (about the
 // cost of a second sort); rows whose n1 exceeds it are "heavy", and pairs of
-// two heavy rows go to the composite pass.
+// two heavy rows go to the composite pass.  The composite pass keeps 32-bit
+// keys of a whole pair in LDS, which holds up to kCompositeMaxN of them;
+// beyond that every pair counts its ties directly (exact, slower only when
+// both rows are heavily tied).
+constexpr int64_t kCompositeMaxN = 16384;
 __host__ __device__ inline int64_t direct_budget(int64_t n) {
+  if (n > kCompositeMaxN) return INT64_MAX;
   int64_t lg = 0;
   while ((1ll << lg) < n) ++lg;
   return 4 * n * lg;
@@ -152,6 +176,7 @@ struct MatDesc {
   const int32_t* status;  // device status word (non-zero: skip all work)
   int32_t* heavy;         // [m] list of heavy rows (written by the heavy pass)
   int32_t* heavy_count;   // device scalar
+  uint64_t* sort_tmp;     // pre-pass sort scratch (rows longer than kLdsSortMax)
   int64_t m;
   int32_t n;
   int32_t scheme;
@@ -165,12 +190,16 @@ struct MatDesc {
 
 // ---- launchers (stream-ordered; return hipError_t)
 
+// sort_tmp: sort_scratch_bytes(m, n) bytes (unused, may be NULL, when n <=
+// kLdsSortMax).
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
                           int32_t* nruns, uint64_t* runs, int32_t* status, bool doubled,
-                          hipStream_t s);
+                          uint64_t* sort_tmp, hipStream_t s);
 
-// Rank pre-pass of every row of every matrix of a descriptor table.
+// Rank pre-pass of every row of every matrix of a descriptor table whose n is
+// at most kLdsSortMax (max_n: the largest such n); longer matrices go
+// through launch_prepass one by one.
 hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t total_rows,
                                 const int64_t* row_prefix_dev, int max_n, hipStream_t s);
 
@@ -192,7 +221,7 @@ hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, int 
 // ---- host helpers shared by the API units (ktau_api.hip)
 
 struct WsLayout {
-  size_t perm, rank, rstart, n1, nruns, runs, heavy, total;
+  size_t perm, rank, rstart, n1, nruns, runs, heavy, sort, total;
   int64_t ld;
 };
 WsLayout ws_layout(int64_t m, int64_t n);

@@ -305,7 +305,8 @@ const char* scheme_name(int s) {
   static const char* names[] = {"wave_k2",   "wave_k4",   "wave_k8",   "wave_k16",  "block_k4",
                                 "block_k8",  "block_k16", "sub8_k16",  "sub16_k16", "sub16_k32",
                                 "sub16_k64", "sub32_k32", "sub32_k64", "wave_k32",  "wave_k64",
-                                "sub8_k32",  "sub8_k64",  "block_k32", "block_k64"};
+                                "sub8_k32",  "sub8_k64",  "block_k32", "block_k64",
+                                "block_k128"};
   static_assert(sizeof(names) / sizeof(names[0]) == kNumSchemes, "one name per scheme");
   return (s >= 0 && s < kNumSchemes) ? names[s] : "invalid";
 }
@@ -320,7 +321,8 @@ int default_scheme(int64_t n) {
   if (n <= 2048) return kWaveK32;
   if (n <= 4096) return kWaveK64;
   if (n <= 8192) return kBlockK32;
-  return kBlockK64;
+  if (n <= 16384) return kBlockK64;
+  return kBlockK128;
 }
 
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
@@ -333,7 +335,9 @@ hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
   }
 #undef KTAU_CASE
   if (e != hipSuccess) return e;
-  // heavy rows, then the composite pass over their pairs
+  // heavy rows, then the composite pass over their pairs (none beyond
+  // kCompositeMaxN: there every pair counts its ties directly)
+  if (d.n > kCompositeMaxN) return hipSuccess;
   hipLaunchKernelGGL(heavy_plain_kernel, dim3(1), dim3(kBlock), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
 #define KTAU_COMP(N, K, G)                                                                    \
@@ -387,6 +391,9 @@ hipError_t launch_heavy(const MatDesc& d, hipStream_t s) {
 
 hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, int max_n,
                                    hipStream_t s) {
+  // matrices longer than kCompositeMaxN have no heavy rows (their budget is
+  // unbounded); the composite kernel for the others holds kCompositeMaxN
+  if (max_n > kCompositeMaxN) max_n = (int)kCompositeMaxN;
   hipLaunchKernelGGL(heavy_batch_kernel, dim3((unsigned)count), dim3(kBlock), 0, s, descs_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

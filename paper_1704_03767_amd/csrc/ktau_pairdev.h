@@ -250,11 +250,11 @@ struct TieWalk {
 
 // Waves per SIMD that the register allocation of a fast-path kernel must
 // allow (the second launch bound; the VGPR file holds 512 per lane): keys and
-// gather indices take K VGPRs, so K = 64 is held to four waves, smaller K to
-// five.
+// gather indices take K VGPRs, so K = 128 is held to two waves, K = 64 to
+// four, smaller K to five.
 template <int K, int G>
 constexpr int fast_waves() {
-  return K >= 64 ? 4 : 5;
+  return K >= 128 ? 2 : K >= 64 ? 4 : 5;
 }
 
 // LDS words per group: the v rank row (uint16), reused for v' on the tie
@@ -297,7 +297,7 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
   const int64_t ld = ry.ld;
   // this lane holds sorted positions k0 .. k0+K-1 (the network's element lane)
   const int k0 = Net::logical_lane(lane) * K;
-  // vector loads stay inside the row (ld is a multiple of 64, so a lane is
+  // vector loads stay inside the row (ld is a multiple of 128, so a lane is
   // either wholly inside or wholly past n)
   const bool in_row = k0 + K <= ld;
   uint16_t* row = (uint16_t*)lds;

@@ -8,10 +8,14 @@
 //
 // One 256-thread workgroup per row.  The row's (value key, sample) pairs are
 // bitonic-sorted in LDS as 64-bit words (order-preserving 32-bit key << 16 |
-// sample), then block scans produce dense ranks and run starts.  Into a pair
+// sample), then block scans produce dense ranks and run starts.  Rows longer
+// than 16384 samples sort their halves in LDS and run part of the last merge
+// level in a global scratch slot.  Into a pair
 // workspace the sample indices and ranks are written doubled (byte offsets
 // into a rank row, and ranks with a free low bit for the pair network's
 // tag); the rank entry point writes them plain.
+#include <limits.h>
+
 #include "ktau_internal.h"
 
 namespace ktau {
@@ -72,68 +76,106 @@ __device__ inline int block_excl_max(int v, int* sh) {
   return max(base, excl_in_wave);
 }
 
-// Ranks row `row` of one matrix; s_keys holds npow2 64-bit words.
-__device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int npow2,
-                            uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
-                            uint16_t* __restrict__ rstart, int64_t ld,
-                            int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
-                            int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
-                            int32_t* __restrict__ status, uint64_t* s_keys, int dbl) {
-  __shared__ int s_scan[kThreads / 64];
-  __shared__ unsigned long long s_n1;
-  const float* x = X + row * (int64_t)n;
-  const int tid = threadIdx.x;
+// Block-wide exclusive suffix scan (min): the minimum of v over the threads
+// after this one (INT_MAX for the last).
+__device__ inline int block_excl_suffix_min(int v, int* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_down(incl, d, 64);
+    if (lane + d < 64) incl = min(incl, t);
+  }
+  int excl_in_wave = __shfl_down(incl, 1, 64);
+  if (lane == 63) excl_in_wave = INT_MAX;
+  if (lane == 0) sh[wave] = incl;
+  __syncthreads();
+  int after = INT_MAX;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w)
+    if (w > wave) after = min(after, sh[w]);
+  __syncthreads();
+  return min(after, excl_in_wave);
+}
 
+// Loads row x as 64-bit sort words (order-preserving key << 16 | sample; all
+// ones past n) for positions base .. base+cnt-1 into s; tells every thread of
+// the block whether a NaN was seen.
+__device__ inline bool load_keys(const float* __restrict__ x, int n, int base, int cnt,
+                                 uint64_t* s) {
   bool any_nan = false;
-  for (int i = tid; i < npow2; i += kThreads) {
+  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+    const int g = base + i;
     uint64_t w = ~0ull;
-    if (i < n) {
+    if (g < n) {
       bool nan;
-      uint32_t k = float_key(x[i], nan);
+      const uint32_t k = float_key(x[g], nan);
       any_nan |= nan;
-      w = ((uint64_t)k << 16) | (uint64_t)i;
+      w = ((uint64_t)k << 16) | (uint64_t)g;
     }
-    s_keys[i] = w;
+    s[i] = w;
   }
-  if (tid == 0) s_n1 = 0;
-  if (__syncthreads_or(any_nan)) {
-    if (tid == 0) atomicExch(status, KTAU_ENAN);
-    return;
-  }
+  return __syncthreads_or(any_nan);
+}
 
-  // Bitonic sort of npow2 64-bit words, ascending.
-  for (int k = 2; k <= npow2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < npow2; i += kThreads) {
-        int p = i ^ j;
+// Compare-exchange stages of an ascending bitonic sort, applied to the cnt
+// words at s that sit at positions base.. of the whole sort: levels (block
+// sizes) k_first .. k_last, the first of them from stage distance j_first
+// down, every later one complete.  A block of size k holding position g runs
+// ascending iff (g & k) == 0.  Every stage distance used must be below cnt.
+__device__ inline void bitonic_stages(uint64_t* s, int cnt, int base, int k_first, int k_last,
+                                      int j_first) {
+  for (int k = k_first; k <= k_last; k <<= 1) {
+    for (int j = (k == k_first ? j_first : k >> 1); j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < cnt; i += kThreads) {
+        const int p = i ^ j;
         if (p > i) {
-          uint64_t a = s_keys[i], b = s_keys[p];
-          bool up = (i & k) == 0;
+          const uint64_t a = s[i], b = s[p];
+          const bool up = ((base + i) & k) == 0;
           if ((a > b) == up) {
-            s_keys[i] = b;
-            s_keys[p] = a;
+            s[i] = b;
+            s[p] = a;
           }
         }
       }
       __syncthreads();
     }
   }
+}
 
+// Passes over the row's npow2 ascending sort words `keys` (LDS, or global
+// scratch for long rows): perm, dense ranks, run starts and n1, then the
+// list of tie runs.
+__device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, int n, int npow2,
+                             uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
+                             uint16_t* __restrict__ rstart, int64_t ld,
+                             int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
+                             int32_t* __restrict__ nruns, uint64_t* __restrict__ runs, int dbl) {
+  __shared__ int s_scan[kThreads / 64];
+  __shared__ unsigned long long s_n1;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_n1 = 0;
+  auto key_at = [&](int k) { return keys[k] >> 16; };
   // Each thread owns `chunk` consecutive sorted positions.
   const int chunk = npow2 / kThreads > 0 ? npow2 / kThreads : 1;
   const int k0 = tid * chunk;
-  // Pass 1: count value changes (for dense ranks) and the last run start.
-  int changes = 0, last_start = 0;
+  // Pass 1: count value changes (for dense ranks); the last and the first
+  // run start after position 0 in the chunk.
+  int changes = 0, last_start = 0, first_change = INT_MAX;
   for (int c = 0; c < chunk; ++c) {
-    int k = k0 + c;
-    if (k < n && k > 0 && (s_keys[k] >> 16) != (s_keys[k - 1] >> 16)) {
+    const int k = k0 + c;
+    if (k < n && k > 0 && key_at(k) != key_at(k - 1)) {
       ++changes;
       last_start = k;
+      first_change = min(first_change, k);
     }
   }
   int total_changes;
-  int rank_base = block_excl_sum(changes, s_scan, total_changes);
-  int start_base = block_excl_max(last_start, s_scan);
+  const int rank_base = block_excl_sum(changes, s_scan, total_changes);
+  const int start_base = block_excl_max(last_start, s_scan);
+  // the first run start after this chunk (n if none): where a run still open
+  // at the chunk's end stops
+  const int next_start = min(block_excl_suffix_min(first_change, s_scan), n);
   // Pass 2: write perm, rank and rstart; accumulate n1.
   uint16_t* prow = perm ? perm + row * ld : nullptr;
   uint16_t* rrow = rank ? rank + row * ld : nullptr;
@@ -141,11 +183,11 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
   int r = rank_base, st = start_base;
   unsigned long long ties = 0;
   for (int c = 0; c < chunk; ++c) {
-    int k = k0 + c;
+    const int k = k0 + c;
     if (k < n) {
-      uint64_t w = s_keys[k];
-      int sample = (int)(w & 0xFFFFu);
-      if (k > 0 && (w >> 16) != (s_keys[k - 1] >> 16)) {
+      const uint64_t w = keys[k];
+      const int sample = (int)(w & 0xFFFFu);
+      if (k > 0 && (w >> 16) != key_at(k - 1)) {
         ++r;
         st = k;
       }
@@ -158,15 +200,15 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
       if (srow) srow[k] = (uint16_t)k;
     }
   }
-  // Padding of rows longer than the sort width (ld > npow2 never happens for
-  // the workspace layout, but callers may pass a wider ld).
+  // Padding of rows longer than the sort width (a workspace row of fewer
+  // than 64 samples is padded to 128).
   for (int k = npow2 + tid; k < ld; k += kThreads) {
     if (prow) prow[k] = (uint16_t)(k << dbl);
     if (srow) srow[k] = (uint16_t)k;
   }
   // Tail positions n..ld-1 map to themselves and rank 0x7FFF (doubled in a
-  // workspace), above every real rank, so the pair kernels gather padding
-  // keys without a bounds test.
+  // workspace), at or above every real rank, so the pair kernels gather
+  // padding keys without a bounds test.
   if (rrow)
     for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)(0x7FFF << dbl);
   atomicAdd(&s_n1, ties);
@@ -177,17 +219,21 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
   }
   if (!runs) return;
   // Pass 3: tie runs of length >= 2, in sorted order.  A thread owns the runs
-  // that start in its chunk; block scans give their index and the number of
-  // within-run pairs of all earlier runs.
-  auto key_at = [&](int k) { return s_keys[k] >> 16; };
+  // that start in its chunk (a run still open at the chunk's end stops at
+  // next_start); block scans give their index and the number of within-run
+  // pairs of all earlier runs.
+  auto run_end = [&](int k) {
+    int e = k + 1;
+    while (e < k0 + chunk && e < n && key_at(e) == key_at(k)) ++e;
+    return e == k0 + chunk && e < n ? next_start : e;
+  };
   int my_runs = 0, my_pairs = 0;
   for (int c = 0; c < chunk; ++c) {
     const int k = k0 + c;
     if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
-      int e = k + 2;
-      while (e < n && key_at(e) == key_at(k)) ++e;
+      const int len = run_end(k) - k;
       ++my_runs;
-      my_pairs += (e - k) * (e - k - 1) / 2;
+      my_pairs += len * (len - 1) / 2;
     }
   }
   int total_runs, total_pairs;
@@ -197,15 +243,69 @@ __device__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int
   for (int c = 0; c < chunk && my_runs > 0; ++c) {
     const int k = k0 + c;
     if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
-      int e = k + 2;
-      while (e < n && key_at(e) == key_at(k)) ++e;
-      const int len = e - k;
+      const int len = run_end(k) - k;
       rrow_runs[run_idx++] =
           ((uint64_t)(uint32_t)pairs << 32) | ((uint64_t)len << 16) | (uint64_t)k;
       pairs += len * (len - 1) / 2;
     }
   }
   if (tid == 0 && nruns) nruns[row] = total_runs;
+}
+
+// Ranks row `row` of one matrix; s_keys holds npow2 <= kLdsSortMax words.
+__device__ __forceinline__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int npow2,
+                            uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
+                            uint16_t* __restrict__ rstart, int64_t ld,
+                            int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
+                            int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
+                            int32_t* __restrict__ status, uint64_t* s_keys, int dbl) {
+  if (load_keys(X + row * (int64_t)n, n, 0, npow2, s_keys)) {
+    if (threadIdx.x == 0) atomicExch(status, KTAU_ENAN);
+    return;
+  }
+  bitonic_stages(s_keys, npow2, 0, 2, npow2, 1);
+  rank_outputs(s_keys, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, dbl);
+}
+
+// A row longer than kLdsSortMax (H), sorted as 2H words: each half is sorted
+// in LDS (the first ascending, the second descending, as the last level
+// wants them) and kept in this workgroup's global slot g (2H words); the last
+// level's first stage pairs the halves there, the rest of it runs per half in
+// LDS again, and the passes read the sorted words from the slot.
+__device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, int64_t row, int n,
+                                 uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
+                                 uint16_t* __restrict__ rstart, int64_t ld,
+                                 int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
+                                 int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
+                                 int32_t* __restrict__ status, uint64_t* s_keys, uint64_t* g,
+                                 int dbl) {
+  constexpr int H = kLdsSortMax;
+  const float* x = X + row * (int64_t)n;
+  for (int h = 0; h < 2; ++h) {
+    if (load_keys(x, n, h * H, H, s_keys)) {
+      if (threadIdx.x == 0) atomicExch(status, KTAU_ENAN);
+      return;
+    }
+    bitonic_stages(s_keys, H, h * H, 2, H, 1);
+    for (int i = threadIdx.x; i < H; i += kThreads) g[h * H + i] = s_keys[i];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < H; i += kThreads) {
+    const uint64_t a = g[i], b = g[H + i];
+    if (a > b) {
+      g[i] = b;
+      g[H + i] = a;
+    }
+  }
+  __syncthreads();
+  for (int h = 0; h < 2; ++h) {
+    for (int i = threadIdx.x; i < H; i += kThreads) s_keys[i] = g[h * H + i];
+    __syncthreads();
+    bitonic_stages(s_keys, H, h * H, 2 * H, 2 * H, H >> 1);
+    for (int i = threadIdx.x; i < H; i += kThreads) g[h * H + i] = s_keys[i];
+    __syncthreads();
+  }
+  rank_outputs(g, row, n, 2 * H, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, dbl);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -221,8 +321,26 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
               s_keys, dbl);
 }
 
+// Long rows: a grid of at most kSortSlots workgroups, each with its own
+// scratch slot of 2 kLdsSortMax words, strides over the rows.
+__global__ void __launch_bounds__(kThreads)
+prepass_long_kernel(const float* __restrict__ X, int64_t m, int n, uint16_t* __restrict__ perm,
+                    uint16_t* __restrict__ rank, uint16_t* __restrict__ rstart, int64_t ld,
+                    int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
+                    int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
+                    int32_t* __restrict__ status, uint64_t* __restrict__ scratch, int dbl) {
+  extern __shared__ uint64_t s_keys[];
+  uint64_t* g = scratch + (int64_t)blockIdx.x * 2 * kLdsSortMax;
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    prepass_row_long(X, row, n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+                     s_keys, g, dbl);
+    __syncthreads();
+  }
+}
+
 // Every row of every matrix of a batch: block b ranks global row b, found by
-// binary search on the per-matrix row prefix.
+// binary search on the per-matrix row prefix.  Rows longer than kLdsSortMax
+// are left to prepass_long_kernel.
 __global__ void __launch_bounds__(kThreads)
 prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
                      const int64_t* __restrict__ row_prefix) {
@@ -235,6 +353,7 @@ prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
     else hi = mid - 1;
   }
   const MatDesc& d = descs[lo];
+  if (d.n > kLdsSortMax) return;
   const int64_t row = g - row_prefix[lo];
   int npow2 = 64;
   while (npow2 < d.n) npow2 <<= 1;
@@ -243,8 +362,8 @@ prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
               (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, s_keys, 1);
 }
 
-// Rows longer than 8192 samples sort 128 KB of keys, above the 64 KB of
-// dynamic LDS a launch gets by default; raise the kernel's limit once.
+// Rows longer than 8192 samples sort 128 KB of keys in LDS, above the 64 KB
+// of dynamic LDS a launch gets by default; raise the kernel's limit.
 template <typename F>
 hipError_t allow_lds(F kernel, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -256,6 +375,7 @@ hipError_t allow_lds(F kernel, size_t bytes) {
 
 hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t total_rows,
                                 const int64_t* row_prefix_dev, int max_n, hipStream_t s) {
+  if (max_n < 1) return hipSuccess;
   int npow2 = 64;
   while (npow2 < max_n) npow2 <<= 1;
   const size_t lds = (size_t)npow2 * sizeof(uint64_t);
@@ -269,7 +389,17 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
                           int32_t* nruns, uint64_t* runs, int32_t* status, bool doubled,
-                          hipStream_t s) {
+                          uint64_t* sort_tmp, hipStream_t s) {
+  if (n > kLdsSortMax) {
+    const size_t lds = (size_t)kLdsSortMax * sizeof(uint64_t);
+    hipError_t e = allow_lds(prepass_long_kernel, lds);
+    if (e != hipSuccess) return e;
+    const int64_t grid = m < kSortSlots ? m : kSortSlots;
+    hipLaunchKernelGGL(prepass_long_kernel, dim3((unsigned)grid), dim3(kThreads), lds, s, X, m,
+                       (int)n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+                       sort_tmp, doubled ? 1 : 0);
+    return hipGetLastError();
+  }
   int npow2 = 64;
   while (npow2 < n) npow2 <<= 1;
   const size_t lds = (size_t)npow2 * sizeof(uint64_t);

@@ -178,6 +178,7 @@ hipError_t query_pairs_t(const QueryDesc& qd, hipStream_t s) {
 
 // Heavy x heavy pairs, on whole waves or 256-lane blocks chosen by n.
 hipError_t query_composite(const QueryDesc& qd, hipStream_t s) {
+  if (qd.n > kCompositeMaxN) return hipSuccess;   // no heavy rows there
 #define KTAU_COMP(K, G) \
   hipLaunchKernelGGL((query_composite_kernel<K, G>), dim3(256), dim3(kBlock), 0, s, qd)
   if (qd.n <= 128) KTAU_COMP(2, 64);

@@ -25,7 +25,7 @@ KTAU_EBUSY = -5
 KTAU_ENAN = -6
 KTAU_ECANCELED = -7
 KTAU_ETIMEDOUT = -8
-KTAU_MAX_N = 16384
+KTAU_MAX_N = 32768
 
 _lock = threading.Lock()
 _lib = None
@@ -51,7 +51,8 @@ def _declare(lib):
         "ktau_pair_to_job": ([i64, i64, i64], i64),
         "ktau_job_to_pair": ([i64, i64, p, p], i32),
         "ktau_tile_to_coord": ([i64, i64, p, p], i32),
-        "ktau_rank": ([p, i64, i64, p, p, p, p, p, p], i32),
+        "ktau_rank": ([p, i64, i64, p, p, p, p, p, p, sz, p], i32),
+        "ktau_rank_workspace_size": ([i64, i64], sz),
         "ktau_allpairs_workspace_size": ([i64, i64], sz),
         "ktau_allpairs": ([p, i64, i64, _PairOut, p, sz, p], i32),
         "ktau_allpairs_range": ([p, i64, i64, i64, i64, _PairOut, p, sz, p], i32),
@@ -166,8 +167,11 @@ def ktau_rank(X: torch.Tensor, stream=None, check: bool = True) -> dict:
     rstart = torch.empty((m, n), dtype=torch.int16, device=dev)
     n1 = torch.empty(m, dtype=torch.int64, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws_bytes = int(lib().ktau_rank_workspace_size(m, n))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev) if ws_bytes else None
     _check(lib().ktau_rank(_ptr(X), m, n, _ptr(perm), _ptr(rank), _ptr(rstart), _ptr(n1),
-                           _ptr(status), _stream(stream)), "ktau_rank")
+                           _ptr(status), _ptr(ws) if ws is not None else None, ws_bytes,
+                           _stream(stream)), "ktau_rank")
     if check:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         st = int(status.item())

@@ -62,9 +62,18 @@ def test_host_side_argument_errors():
                               None) == K.KTAU_EINVAL
     assert L.ktau_allpairs_workspace_size(1, 10) == 0
     assert L.ktau_allpairs_workspace_size(10, K.KTAU_MAX_N + 1) == 0
-    assert L.ktau_rank(None, 3, 3, None, None, None, None, fake, None) == K.KTAU_EINVAL
-    assert L.ktau_rank(fake, 3, K.KTAU_MAX_N + 1, None, None, None, None, fake,
+    assert L.ktau_rank(None, 3, 3, None, None, None, None, fake, None, 0, None) == K.KTAU_EINVAL
+    assert L.ktau_rank(fake, 3, K.KTAU_MAX_N + 1, None, None, None, None, fake, None, 0,
                        None) == K.KTAU_ERANGE
+    # rows longer than 16384 need sort scratch: missing, misaligned, too small
+    need = L.ktau_rank_workspace_size(3, 20000)
+    assert need >= 3 * 32768 * 8 and L.ktau_rank_workspace_size(3, 16384) == 0
+    assert L.ktau_rank(fake, 3, 20000, None, None, None, None, fake, None, need,
+                       None) == K.KTAU_EINVAL
+    assert L.ktau_rank(fake, 3, 20000, None, None, None, None, fake, ctypes.c_void_p(0x1008), need,
+                       None) == K.KTAU_EINVAL
+    assert L.ktau_rank(fake, 3, 20000, None, None, None, None, fake, fake, need - 1,
+                       None) == K.KTAU_ENOMEM
     assert L.ktau_pair_to_job(10, 3, 3) == -1
     assert L.ktau_pair_to_job(10, 4, 3) == -1
     assert L.ktau_pair_to_job(10, 3, 10) == -1

@@ -49,7 +49,7 @@ def test_batch_matches_oracle_and_plain(use_graph, tmp_path):
 def test_batch_with_large_samples():
     # classes of 256-lane schemes next to small ones; the pre-pass and the
     # composite pass are sized by the largest n of the batch
-    shapes = [(21, 16384), (3, 9000), (40, 300), (2, 8192), (17, 4097)]
+    shapes = [(21, 16384), (3, 9000), (40, 300), (2, 8192), (17, 4097), (9, 17941), (2, 32768)]
     mats = [synth.batch_matrix(s, 47, i) for i, s in enumerate(shapes)]
     mats[1][1] = np.floor(mats[1][1])                 # a heavily tied row
     mats[1][2] = np.round(mats[1][2])

@@ -52,7 +52,7 @@ def _lehmer_perm(rng, n):
     return perm, int(code.sum())
 
 
-@pytest.mark.parametrize("n", [2, 3, 64, 129, 1024, 1025, 4096, 8193, 16384])
+@pytest.mark.parametrize("n", [2, 3, 64, 129, 1024, 1025, 4096, 8193, 16384, 17941, 32768])
 def test_permutation_inversions_closed_form(n):
     rng = np.random.default_rng(n)
     rows, want = [np.arange(n, dtype=np.float32)], []

@@ -68,7 +68,8 @@ def _oracle_rstart(order, rank):
 
 
 @pytest.mark.parametrize("shape_seed", [(64, 128, 1), (33, 1000, 2), (17, 4096, 3), (5, 2, 4),
-                                        (6, 8193, 6), (5, 16384, 7),
+                                        (6, 8193, 6), (5, 16384, 7), (4, 16385, 8),
+                                        (6, 17941, 9), (3, 32768, 10),
                                         (9, 65, 5)])
 def test_prepass_matches_oracle(shape_seed):
     m, n, seed = shape_seed
@@ -154,8 +155,10 @@ def test_block_schemes_on_edges(n):
             _check_full(X, scheme=scheme)
 
 
-# Samples beyond 4096 run on 256-lane blocks with 32 or 64 keys per lane.
-LARGE_N = [4097, 5000, 8191, 8192, 8193, 12289, 16383, 16384]
+# Samples beyond 4096 run on 256-lane blocks with 32, 64 or 128 keys per lane;
+# beyond 16384 the pre-pass merges in global scratch and every pair counts its
+# ties directly.
+LARGE_N = [4097, 5000, 8191, 8192, 8193, 12289, 16383, 16384, 16385, 17941, 24000, 32767, 32768]
 
 
 @pytest.mark.parametrize("n", LARGE_N)
@@ -170,7 +173,7 @@ def test_large_sample_counts(n):
             _check_full(X, scheme=scheme, q=2)
 
 
-@pytest.mark.parametrize("n", [6000, 16384])
+@pytest.mark.parametrize("n", [6000, 16384, 17941])
 def test_large_gene_expression_tiles(n):
     # several tiles and a ragged tail of rows, rows with 2% exact zeros
     X = synth.lognormal_blocks(37, n, 60 + n % 7)
@@ -180,7 +183,7 @@ def test_large_gene_expression_tiles(n):
 
 def test_large_heavy_tie_paths():
     rng = np.random.default_rng(23)
-    for n in (5000, 16384):
+    for n in (5000, 16384, 20000):
         rows = [rng.integers(0, lv, n).astype(np.float32) for lv in (2, 3, 8, 200, 3000)]
         rows.append(np.where(rng.random(n) < 0.9, 0.0, rng.standard_normal(n)).astype(np.float32))
         rows.append(rng.standard_normal(n).astype(np.float32))

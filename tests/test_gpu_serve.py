@@ -71,7 +71,7 @@ def test_query_every_scheme(monkeypatch):
         kdb.close()
 
 
-@pytest.mark.parametrize("n", [8192, 16384])
+@pytest.mark.parametrize("n", [8192, 16384, 24000])
 def test_query_large_samples(n):
     db = _db(m=120, n=n, seed=58)
     Q = _queries(db, 3, 59)
