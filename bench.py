@@ -31,6 +31,9 @@ CLOCK_HZ = 2.4e9
 # Integer VALU: 4 SIMDs per CU, each retiring one 64-lane wave instruction
 # every 4 cycles = 64 int32 lane-ops per CU per cycle.
 INT_VALU_OPS = CUS * 64 * CLOCK_HZ           # 3.93e13 lane-ops/s
+# The paper's VSE kernel on one Xeon Phi 5110P for its 17,941 x 353 dataset
+# (Table 4: 296 s), as strict pairs per second: context, not a target.
+PAPER_PHI_DS3526 = 17941 * 17940 / 2 / 296.0
 
 
 def merge_steps(n: int) -> int:
@@ -150,6 +153,51 @@ def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
             "plans": [f"{s}/q{q}" for s, q in classes]}
 
 
+def plain_timing(K, torch, stream, X, reps: int) -> dict:
+    """Mean time of the plain path (pre-pass + pair kernel) on matrix X."""
+    Xd = torch.from_numpy(X).cuda()
+    m, n = X.shape
+    P = m * (m - 1) // 2
+    out = K.alloc_outputs(P, m, Xd.device)
+    ws = K.alloc_workspace(m, n, Xd.device)
+
+    def step():
+        K.ktau_prepare(Xd, ws, out["n1"], stream=stream)
+        K.ktau_pairs(m, n, out, ws, stream=stream)
+
+    step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    if K.ktau_status(ws) != K.KTAU_OK:
+        raise RuntimeError(f"plain call on {m} x {n} failed")
+    ms = e0.elapsed_time(e1) / reps
+    return {"m": m, "n": n, "pairs": P, "ms": ms, "pairs_per_s": P / (ms * 1e-3),
+            "scheme": K.ktau_scheme_names()[K.ktau_default_scheme(n)],
+            "merge_steps_per_s": P * merge_steps(n) / (ms * 1e-3)}
+
+
+def other_shapes(K, synth, torch, stream, reps: int) -> dict:
+    """The paper's two orientations of its gene-expression data: genes as
+    variables (m = 17,941, n = 353, as its timed datasets; its one-Phi VSE
+    rate for that shape, derived from Table 4, is context) and samples as
+    variables (m = 353, n = 17,941, beyond the 16-bit rank packing of the
+    fast merge until 32,768)."""
+    genes = plain_timing(K, torch, stream, synth.lognormal_blocks(17941, 353, 7), reps)
+    genes["workload"] = ("gene-vs-gene m=17941 n=353 log-normal, blocks of 64 rows at rho=0.6, "
+                         "2% exact zeros, seed 7")
+    genes["paper_phi_vse_pairs_per_s"] = PAPER_PHI_DS3526
+    samples = plain_timing(K, torch, stream, synth.samples_matrix(353, 17941, 6), reps)
+    samples["workload"] = ("sample-vs-sample m=353 n=17941: per-gene level + 4 group offsets + "
+                           "noise, exp, 2% exact zeros, seed 6")
+    return {"gene_vs_gene": genes, "sample_vs_sample": samples}
+
+
 def serving(K, synth, torch, stream, seconds: float) -> dict:
     """Query-vs-database search over a resident 20000 x 800 log-normal
     database (seed 5): requests of 1-64 query rows, top-100 by |tau_B|.
@@ -258,6 +306,8 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch comparison (256 matrices)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip the gene-vs-gene and sample-vs-sample shapes")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="target length of each Poisson run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -385,6 +435,8 @@ def main() -> int:
     }
     if not args.no_uneven:
         result["uneven_batch"] = uneven_batch(K, synth, torch, stream, max(2, args.steps))
+    if not args.no_shapes:
+        result["shapes"] = other_shapes(K, synth, torch, stream, max(2, args.steps))
     if not args.no_serve:
         result["serving"] = serving(K, synth, torch, stream, args.serve_seconds)
         rates = result["serving"]["at_rates"]

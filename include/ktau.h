@@ -143,7 +143,8 @@ int ktau_allpairs_range(const float* X_dev, int64_t m, int64_t n,
  * into the workspace (writing out_n1_dev[m] too if it is not NULL).
  * ktau_pairs computes jobs [J_begin, J_end) (J_begin < 0: all jobs, in tile
  * order) from a workspace prepared for the same (m, n); scheme < 0 and q <= 0
- * pick the defaults. */
+ * pick the defaults (ktau_default_scheme(n); tile edge 8 for n <= 4096, 4 for
+ * n <= 16384, else 2). */
 int ktau_prepare(const float* X_dev, int64_t m, int64_t n, int64_t* out_n1_dev,
                  void* workspace_dev, size_t ws_bytes, void* stream);
 int ktau_pairs(int64_t m, int64_t n, int64_t J_begin, int64_t J_end,
@@ -205,7 +206,8 @@ void ktau_batch_default_opts(ktau_batch_opts* opts_host);
 
 /* Validates every matrix, chooses each one's (scheme, q), and allocates the
  * plan's device arena (rank workspaces for all matrices plus descriptors;
- * about 6 m ceil64(n) bytes per matrix).  The matrices' X_dev and output
+ * about 10 m ceil128(n) bytes per matrix, plus 256 KB per row, for at most
+ * 256 rows, of sort scratch where n > 16384).  The matrices' X_dev and output
  * arrays are the caller's and must stay valid while the plan is used.
  * Autotuning, when a sample-count class is not yet tuned, times the
  * candidates on the first rows of the class's matrix with the most rows

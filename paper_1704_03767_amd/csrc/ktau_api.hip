@@ -120,7 +120,7 @@ int check_pairs(int64_t m, int64_t n, int64_t& J_begin, int64_t& J_end, int& sch
   if (J_begin > J_end || J_end > P) return KTAU_ERANGE;
   if (scheme < 0) scheme = env_int("KTAU_FORCE_SCHEME", default_scheme(n));
   if (scheme < 0 || scheme >= kNumSchemes || scheme_capacity(scheme) < n) return KTAU_EINVAL;
-  if (q <= 0) q = env_int("KTAU_TILE_Q", 8);
+  if (q <= 0) q = env_int("KTAU_TILE_Q", default_q(n));
   if (q < 1 || q > 64) return KTAU_EINVAL;
   return KTAU_OK;
 }

@@ -125,7 +125,7 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     rc = KTAU_ENOMEM;
   }
-  Plan best{default_scheme(n), 8, 0.0};
+  Plan best{default_scheme(n), default_q(n), 0.0};
   if (rc == KTAU_OK) {
     if (!src)
       hipLaunchKernelGGL(synth_kernel, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, X,
@@ -138,7 +138,8 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
     ktau_pair_out out{};
     out.tau_b = tau;
     for (int scheme : candidates(cls)) {
-      for (int q : {4, 8, 16}) {
+      const int q0 = default_q(n);
+      for (int q : {q0 / 2, q0, 2 * q0}) {
         MatDesc d = matdesc(ws, m, n, out, scheme, q, 0, P, nullptr);
         float best_ms = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
@@ -172,7 +173,7 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
 Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* rc,
               const float* rep = nullptr, int64_t m_rep = 0, int64_t n_rep = 0) {
   const int64_t cls = n_class(n);
-  if (!autotune) return Plan{default_scheme(n), env_int("KTAU_TILE_Q", 8), 0.0};
+  if (!autotune) return Plan{default_scheme(n), env_int("KTAU_TILE_Q", default_q(n)), 0.0};
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_tuned.find(cls);
   if (it == g_tuned.end()) {
@@ -181,7 +182,7 @@ Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* r
   }
   if (it == g_tuned.end()) {
     *rc = tune_class(cls, rep, m_rep, n_rep, s);
-    if (*rc != KTAU_OK) return Plan{default_scheme(n), 8, 0.0};
+    if (*rc != KTAU_OK) return Plan{default_scheme(n), default_q(n), 0.0};
     save_cache(cache);
     it = g_tuned.find(cls);
   }

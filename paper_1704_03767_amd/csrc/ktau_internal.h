@@ -152,6 +152,9 @@ inline int scheme_k(int s) {
 inline int64_t scheme_capacity(int s) { return (int64_t)scheme_lanes(s) * scheme_k(s); }
 const char* scheme_name(int s);
 int default_scheme(int64_t n);
+// Default tile edge: 8 up to n = 4096; longer rows take one 256-lane block per
+// pair and are few (m is small next to n), so smaller tiles spread them.
+int default_q(int64_t n);
 
 // Comparisons the direct in-run tie count may spend on one pair (about the
 // cost of a second sort); rows whose n1 exceeds it are "heavy", and pairs of

@@ -325,6 +325,8 @@ int default_scheme(int64_t n) {
   return kBlockK128;
 }
 
+int default_q(int64_t n) { return n <= 4096 ? 8 : n <= 16384 ? 4 : 2; }
+
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
   hipError_t e;
 #define KTAU_CASE(S, K, G) \

@@ -72,6 +72,25 @@ def lognormal_blocks(m: int, n: int, seed: int, block: int = 64, rho: float = 0.
     return X
 
 
+def samples_matrix(m: int = 353, n: int = 17941, seed: int = 6, groups: int = 4,
+                   gene_sd: float = 1.5, group_sd: float = 0.5, noise_sd: float = 0.5,
+                   zero_frac: float = 0.02) -> np.ndarray:
+    """Sample-vs-sample orientation (rows = samples, columns = genes): log
+    expression = a per-gene level shared by every sample, N(0, gene_sd^2),
+    plus a per-(group, gene) offset, N(0, group_sd^2), for the sample's group
+    (sample s is in group s mod groups), plus noise, N(0, noise_sd^2); X is its
+    exponential with a Bernoulli(zero_frac) subset of entries set to exactly 0
+    (dropouts).  Rows are strongly and unevenly correlated, as samples over
+    shared genes are."""
+    rng = np.random.default_rng(seed)
+    level = rng.standard_normal(n) * gene_sd
+    offset = rng.standard_normal((groups, n)) * group_sd
+    Z = level + offset[np.arange(m) % groups] + rng.standard_normal((m, n)) * noise_sd
+    X = np.exp(Z)
+    X[rng.random((m, n)) < zero_frac] = 0.0
+    return X.astype(np.float32)
+
+
 def config_matrix(cfg: int, seed: int | None = None) -> np.ndarray:
     """The single-matrix workloads 1-3."""
     seed = DEFAULT_SEEDS[cfg] if seed is None else seed

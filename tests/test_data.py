@@ -51,6 +51,22 @@ def test_gene_expression_blocks_have_the_stated_correlation():
     assert 0.85 < tau[~same].std() / _null_sd(n) < 1.1
 
 
+def test_sample_orientation_correlations():
+    # rows = samples over shared genes: log-expression correlation is
+    # (gene + group variance) / total within a group and gene / total across
+    # groups; the Gaussian-copula closed form and the zero shrinkage as above
+    X = synth.samples_matrix(24, 17941, 6)
+    assert X.shape == (24, 17941) and abs((X == 0).mean() - 0.02) < 0.001
+    res = oracle.allpairs(X)
+    ys, xs = oracle.enumerate_pairs(24)
+    same = ys % 4 == xs % 4
+    g2, c2, e2 = 1.5 ** 2, 0.5 ** 2, 0.5 ** 2
+    shrink = (1 - 0.02) ** 4
+    for sel, rho in ((same, (g2 + c2) / (g2 + c2 + e2)), (~same, g2 / (g2 + c2 + e2))):
+        want = (2 / math.pi) * math.asin(rho) * shrink
+        assert abs(res["tau_b"][sel].mean() - want) < 0.01, (res["tau_b"][sel].mean(), want)
+
+
 def test_medium_workload_quantised_rows():
     X = synth.config_matrix(2)
     m, n = X.shape

@@ -287,6 +287,31 @@ def test_gene_expression_scale_sampled():
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("shape", ["gene_vs_gene", "sample_vs_sample"])
+def test_paper_orientations_sampled(shape):
+    # the paper's data in both orientations, as bench.py times them:
+    # m = 17941 genes x n = 353 samples, and m = 353 samples x n = 17941 genes
+    if shape == "gene_vs_gene":
+        X = synth.lognormal_blocks(17941, 353, 7)
+    else:
+        X = synth.samples_matrix(353, 17941, 6)
+    m, n = X.shape
+    Xd = torch.from_numpy(X).cuda()
+    out = K.ktau_allpairs(Xd)
+    P = m * (m - 1) // 2
+    rng = np.random.default_rng(44)
+    J = np.unique(np.concatenate([rng.integers(0, P, 3000), [0, P - 1]]))
+    Jd = torch.from_numpy(J).cuda()
+    got = {k: out[k][Jd].cpu().numpy() for k in ("nc", "nd", "n3", "tau_b")}
+    yx = np.array([K.ktau_job_to_pair(m, int(j)) for j in J])
+    want = oracle.pairs(X, yx[:, 0], yx[:, 1], "gse")
+    _assert_same(got, want)
+    assert np.array_equal(out["n1"].cpu().numpy(), oracle.rank_rows(X)["n1"])
+    tb = out["tau_b"]
+    assert bool((tb.abs() <= 1.0).all()) and not bool(tb.isnan().any())
+
+
+@pytest.mark.slow
 def test_gene_expression_scale_batched_equals_plain():
     # the launch configuration bench.py reports as its value: a one-matrix
     # batched plan (autotuned scheme, persistent kernel, hipGraph), replayed
