@@ -66,7 +66,7 @@ struct Net {
   static constexpr int N = K * G;
   // VGPRs exchanged per LDS round across the waves of a 256-lane group (the
   // exchange buffer holds kXChunk * G words)
-  static constexpr int kXChunk = KV < 16 ? KV : 16;
+  static constexpr int kXChunk = KV < 16 ? KV : K >= 128 ? 8 : 16;
   static_assert(K >= 2 && K <= 128 && (K & (K - 1)) == 0, "K is a power of two <= 128");
   // Lane-spanning levels accumulate sum(raw * r) below bit kWShift and the
   // number of raw tags above it (sum of r < K is at most K(K-1)/2).

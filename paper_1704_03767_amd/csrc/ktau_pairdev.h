@@ -338,6 +338,10 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
     t.x = *(const uint16_t*)(rowb + a);
     t.y = *(const uint16_t*)(rowb + b);
     key[j] = t;
+    // with 128 keys per lane, keep the scheduler from putting every gather
+    // load in flight at once (each needs a register until it is packed)
+    if constexpr (K >= 128)
+      if (j % 16 == 15) __builtin_amdgcn_sched_barrier(0);
   }
   uint32_t xin = 0, tie = 0;
   if (n1u != 0) {
