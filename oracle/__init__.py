@@ -12,11 +12,16 @@ Two pair routines, both from the paper:
     merge of Algorithm 2.
 tau_B (Eq. 3) and tau_A (Eq. 1) follow from the integer counts.
 
+Also a permutation test of tau (Sec. 1 names it for P-values): the samples of
+a pair's second row are permuted by caller-given permutations.
+
 Pins (tests/test_oracle.py): brute == gse on exhaustive tiny domains; closed
 forms (inversion count of a permutation built from its Lehmer code, reversal,
 adjacent swap); invariants (self = 1, negation = -1, symmetry, sample
 permutation, exact monotone maps, partition identity); scipy.stats.kendalltau
-and numpy.unique tie-group counts as independent library routines.
+and numpy.unique tie-group counts as independent library routines; for the
+permutation test, identity permutations, the Mahonian distribution of the
+inversion count over all permutations, and the definition in plain Python.
 """
 from __future__ import annotations
 
@@ -83,6 +88,8 @@ def _load():
         lib.ko_rank_rows.restype = i32
         lib.ko_query_topk.argtypes = [p, i64, i64, p, i64, i64, i32, p, p, p]
         lib.ko_query_topk.restype = i32
+        lib.ko_perm_test.argtypes = [p, i64, i64, p, i64, p, p, i64, i32, i32, p, p]
+        lib.ko_perm_test.restype = i32
         lib.ko_enumerate_pairs.argtypes = [i64, p, p]
         lib.ko_enumerate_pairs.restype = i32
         lib.ko_max_threads.argtypes = []
@@ -178,6 +185,27 @@ def pairs(X, ys, xs, method: str = "gse", threads: int = 0) -> dict:
     )
     _check(rc, "ko_pairs")
     return out
+
+
+def perm_test(X, perms, ys, xs, method: str = "gse", threads: int = 0) -> dict:
+    """Permutation test of pairs (ys[i], xs[i]): the samples of row xs[i] are
+    permuted by each row of perms (B x n); count of permutations with
+    |n_c - n_d| >= the observed one, and P = (1 + count) / (B + 1)."""
+    lib = _load()
+    X = _f32(X)
+    m, n = X.shape
+    perms = np.ascontiguousarray(perms, dtype=np.uint16)
+    if perms.ndim != 2 or perms.shape[1] != n:
+        raise OracleError("perms must be B x n")
+    ys = np.ascontiguousarray(ys, dtype=np.int64)
+    xs = np.ascontiguousarray(xs, dtype=np.int64)
+    cnt = ys.size
+    count = np.empty(cnt, np.int64)
+    p = np.empty(cnt, np.float64)
+    rc = lib.ko_perm_test(_ptr(X), m, n, _ptr(perms), perms.shape[0], _ptr(ys), _ptr(xs), cnt,
+                          METHODS[method], int(threads), _ptr(count), _ptr(p))
+    _check(rc, "ko_perm_test")
+    return {"count": count, "p": p}
 
 
 def rank_rows(X) -> dict:

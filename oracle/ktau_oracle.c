@@ -27,7 +27,11 @@
  *   - tau_B = (double)(nc-nd) / sqrt((double)(n0-n1) * (double)(n0-n2)),
  *     IEEE round-to-nearest, no fused multiply-add; 0/0 gives NaN;
  *   - the all-pairs output is the strict upper triangle (y < x), numbered
- *     row-major (Sec. 4.1 numbering with the diagonal left out).
+ *     row-major (Sec. 4.1 numbering with the diagonal left out);
+ *   - the permutation test (Sec. 1 mentions it for P-values) permutes the
+ *     samples of the pair's second row by caller-given permutations and
+ *     counts those with |n_c - n_d| at least the observed one; the P-value is
+ *     (1 + count) / (B + 1).
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC -ffp-contract=off (no fast-math).
  */
@@ -334,6 +338,78 @@ int ko_pairs(const float* X, int64_t m, int64_t n, const int64_t* ys,
     free(work);
   }
   if (fail == 2) return KO_ENAN;
+  return fail ? KO_ENOMEM : KO_OK;
+}
+
+/* ---- permutation test (Sec. 1: P-values of tau by permutation test) ----- */
+
+/* 1 if row b of perms (n entries) is a permutation of 0..n-1. */
+static int ko_is_permutation(const uint16_t* p, int64_t n, unsigned char* seen) {
+  memset(seen, 0, (size_t)n);
+  for (int64_t t = 0; t < n; ++t) {
+    if ((int64_t)p[t] >= n || seen[p[t]]) return 0;
+    seen[p[t]] = 1;
+  }
+  return 1;
+}
+
+/* For selected pairs (ys[i], xs[i]): S = n_c - n_d of u = row ys[i] against
+ * v = row xs[i], and S_b of u against v with its samples permuted by each of
+ * the B permutations (v_b[t] = v[perms[b n + t]]).  count_out[i] = number of
+ * b with |S_b| >= |S|; p_out[i] = (1 + count) / (B + 1).  The two tie terms
+ * of tau_B do not change when v's samples are permuted, so |tau_B| orders the
+ * permutations as |S| does. */
+int ko_perm_test(const float* X, int64_t m, int64_t n, const uint16_t* perms, int64_t B,
+                 const int64_t* ys, const int64_t* xs, int64_t count, int method,
+                 int threads, int64_t* count_out, double* p_out) {
+  if (m < 1 || n < 2 || !X || !perms || B < 1 || count < 0) return KO_EINVAL;
+  for (int64_t i = 0; i < count; ++i)
+    if (ys[i] < 0 || ys[i] >= m || xs[i] < 0 || xs[i] >= m) return KO_EINVAL;
+  if (ko_has_nan(X, m * n)) return KO_ENAN;
+  unsigned char* seen = (unsigned char*)malloc((size_t)n);
+  if (!seen) return KO_ENOMEM;
+  for (int64_t b = 0; b < B; ++b)
+    if (!ko_is_permutation(perms + b * n, n, seen)) {
+      free(seen);
+      return KO_EINVAL;
+    }
+  free(seen);
+  int fail = 0;
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#else
+  (void)threads;
+#endif
+#pragma omp parallel
+  {
+    ko_joint* work = (ko_joint*)malloc((size_t)(2 * n) * sizeof(ko_joint));
+    float* vb = (float*)malloc((size_t)n * sizeof(float));
+    if (!work || !vb) {
+#pragma omp atomic write
+      fail = 1;
+    }
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < count; ++i) {
+      if (!work || !vb) continue;
+      const float* u = X + ys[i] * n;
+      const float* v = X + xs[i] * n;
+      ko_counts c;
+      if (method == 0) ko_pair_brute(u, v, n, &c);
+      else ko_pair_gse_work(u, v, n, &c, work);
+      const int64_t s_obs = llabs(c.nc - c.nd);
+      int64_t ge = 0;
+      for (int64_t b = 0; b < B; ++b) {
+        for (int64_t t = 0; t < n; ++t) vb[t] = v[perms[b * n + t]];
+        if (method == 0) ko_pair_brute(u, vb, n, &c);
+        else ko_pair_gse_work(u, vb, n, &c, work);
+        if (llabs(c.nc - c.nd) >= s_obs) ++ge;
+      }
+      count_out[i] = ge;
+      if (p_out) p_out[i] = (double)(1 + ge) / (double)(B + 1);
+    }
+    free(work);
+    free(vb);
+  }
   return fail ? KO_ENOMEM : KO_OK;
 }
 

@@ -275,6 +275,95 @@ struct FastLds {
   }
 };
 
+// v'[k] = rank_v[perm_u[k]] for this lane's K sorted positions, from a rank
+// row staged in LDS (row) and the lane's perm words (pw, byte offsets).
+template <int K>
+__device__ __forceinline__ void gather_keys(const uint16_t* row, const uint32_t (&pw)[K / 2],
+                                            bitonic::u16x2 (&key)[K / 2]) {
+  using bitonic::u16x2;
+  constexpr int KV = K / 2;
+  // v'[k] = rank_v[perm_u[k]], packed: VGPR j holds k0 + j and k0 + j + KV.
+  // Workspace ranks are stored doubled, so the gathered values are already
+  // the network's keys 2 v' (its tag goes in bit 0); row tails past n hold
+  // perm[k] = 2k and 0xFFFE, the padding key.
+  const char* rowb = (const char*)row;
+#pragma unroll
+  for (int j = 0; j < KV; ++j) {
+    const uint32_t a = j % 2 ? pw[j / 2] >> 16 : pw[j / 2] & 0xFFFFu;
+    const uint32_t b = (j + KV) % 2 ? pw[(j + KV) / 2] >> 16 : pw[(j + KV) / 2] & 0xFFFFu;
+    u16x2 t;
+    t.x = *(const uint16_t*)(rowb + a);
+    t.y = *(const uint16_t*)(rowb + b);
+    key[j] = t;
+    // with 128 keys per lane, keep the scheduler from putting every gather
+    // load in flight at once (each needs a register until it is packed)
+    if constexpr (K >= 128)
+      if (j % 16 == 15) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// n_d and n3 of one pair from its gathered keys: the direct in-run tie count
+// over u's runs (when u has ties: the LDS row is overwritten with 2 v' in u
+// order), then the network's inversion count less the inversions inside u
+// runs.  Called by every lane of the group.
+template <int K, int G>
+__device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uint16_t* row,
+                                               bool in_row, int k0, const RankView& ru_v,
+                                               int64_t u, int64_t n1u, uint32_t* xbuf,
+                                               uint32_t* red, int lane, uint32_t& nd,
+                                               uint32_t& n3) {
+  using Net = bitonic::Net<K, G>;
+  constexpr int KV = K / 2;
+  const int64_t ld = ru_v.ld;
+  uint32_t xin = 0, tie = 0;
+  if (n1u != 0) {
+    // 2 v' in u order replaces the rank row once every lane has gathered
+    group_sync<G>();
+    if (in_row) {
+      uint32_t w[KV];
+      if constexpr (KV == 1) {
+        w[0] = bitonic::bits(key[0]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < KV / 2; ++i) {
+          // positions k0 + 2i, 2i + 1 (low halves), k0 + KV + 2i, 2i + 1 (high)
+          w[i] = __builtin_amdgcn_perm(bitonic::bits(key[2 * i + 1]), bitonic::bits(key[2 * i]),
+                                       0x05040100u);
+          w[KV / 2 + i] = __builtin_amdgcn_perm(bitonic::bits(key[2 * i + 1]),
+                                                bitonic::bits(key[2 * i]), 0x07060302u);
+        }
+      }
+      store_words<K>(row + k0, w);
+    }
+    group_sync<G>();
+    // The n1_u pairs of positions inside one tie run of u (Step 2), split
+    // evenly into 2G stretches; lane l walks stretches l and l + G side by
+    // side so that the LDS loads of the two walks overlap.
+    const uint64_t* rl = ru_v.runs + u * (ld / 2);
+    const int nr = ru_v.nruns[u];
+    const uint32_t total = (uint32_t)n1u;
+    const uint32_t per = (total + 2 * G - 1) / (2 * G);
+    const uint32_t p0 = (uint32_t)lane * per, p1 = (uint32_t)(lane + G) * per;
+    const uint32_t c0 = p0 < total ? (total - p0 < per ? total - p0 : per) : 0u;
+    const uint32_t c1 = p1 < total ? (total - p1 < per ? total - p1 : per) : 0u;
+    if (c0 > 0) {
+      TieWalk w0, w1;
+      w0.init(rl, nr, p0, row);
+      if (c1 > 0) w1.init(rl, nr, p1, row);
+      for (uint32_t i = 0; i < c0; ++i) {
+        w0.step(row, i + 1 < c0, xin, tie);
+        if (i < c1) w1.step(row, i + 1 < c1, xin, tie);
+      }
+    }
+  }
+  // n_d = inversions - inversions inside u runs, summed in one reduction
+  // (exact modulo 2^32)
+  const uint32_t share = Net::count(key, lane, xbuf) - xin;
+  nd = group_sum<G>(share, red);
+  n3 = n1u != 0 ? group_sum<G>(tie, red) : 0u;
+}
+
+
 // n_d and n3 of rows (y, x) unless both rows exceed the tie budget (then
 // returns false and the composite pass handles the pair).  Called by every
 // lane of the group with the same arguments.
@@ -324,71 +413,9 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
     store_words<K>(row + k0, w);
   }
   group_sync<G>();
-  // v'[k] = rank_v[perm_u[k]], packed: VGPR j holds k0 + j and k0 + j + KV.
-  // Workspace ranks are stored doubled, so the gathered values are already
-  // the network's keys 2 v' (its tag goes in bit 0); row tails past n hold
-  // perm[k] = 2k and 0xFFFE, the padding key.
-  const char* rowb = (const char*)row;
   u16x2 key[KV];
-#pragma unroll
-  for (int j = 0; j < KV; ++j) {
-    const uint32_t a = j % 2 ? pw[j / 2] >> 16 : pw[j / 2] & 0xFFFFu;
-    const uint32_t b = (j + KV) % 2 ? pw[(j + KV) / 2] >> 16 : pw[(j + KV) / 2] & 0xFFFFu;
-    u16x2 t;
-    t.x = *(const uint16_t*)(rowb + a);
-    t.y = *(const uint16_t*)(rowb + b);
-    key[j] = t;
-    // with 128 keys per lane, keep the scheduler from putting every gather
-    // load in flight at once (each needs a register until it is packed)
-    if constexpr (K >= 128)
-      if (j % 16 == 15) __builtin_amdgcn_sched_barrier(0);
-  }
-  uint32_t xin = 0, tie = 0;
-  if (n1u != 0) {
-    // 2 v' in u order replaces the rank row once every lane has gathered
-    group_sync<G>();
-    if (in_row) {
-      uint32_t w[KV];
-      if constexpr (KV == 1) {
-        w[0] = bitonic::bits(key[0]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < KV / 2; ++i) {
-          // positions k0 + 2i, 2i + 1 (low halves), k0 + KV + 2i, 2i + 1 (high)
-          w[i] = __builtin_amdgcn_perm(bitonic::bits(key[2 * i + 1]), bitonic::bits(key[2 * i]),
-                                       0x05040100u);
-          w[KV / 2 + i] = __builtin_amdgcn_perm(bitonic::bits(key[2 * i + 1]),
-                                                bitonic::bits(key[2 * i]), 0x07060302u);
-        }
-      }
-      store_words<K>(row + k0, w);
-    }
-    group_sync<G>();
-    // The n1_u pairs of positions inside one tie run of u (Step 2), split
-    // evenly into 2G stretches; lane l walks stretches l and l + G side by
-    // side so that the LDS loads of the two walks overlap.
-    const uint64_t* rl = ru_v.runs + u * (ld / 2);
-    const int nr = ru_v.nruns[u];
-    const uint32_t total = (uint32_t)n1u;
-    const uint32_t per = (total + 2 * G - 1) / (2 * G);
-    const uint32_t p0 = (uint32_t)lane * per, p1 = (uint32_t)(lane + G) * per;
-    const uint32_t c0 = p0 < total ? (total - p0 < per ? total - p0 : per) : 0u;
-    const uint32_t c1 = p1 < total ? (total - p1 < per ? total - p1 : per) : 0u;
-    if (c0 > 0) {
-      TieWalk w0, w1;
-      w0.init(rl, nr, p0, row);
-      if (c1 > 0) w1.init(rl, nr, p1, row);
-      for (uint32_t i = 0; i < c0; ++i) {
-        w0.step(row, i + 1 < c0, xin, tie);
-        if (i < c1) w1.step(row, i + 1 < c1, xin, tie);
-      }
-    }
-  }
-  // n_d = inversions - inversions inside u runs, summed in one reduction
-  // (exact modulo 2^32)
-  const uint32_t share = Net::count(key, lane, xbuf) - xin;
-  nd = group_sum<G>(share, red);
-  n3 = n1u != 0 ? group_sum<G>(tie, red) : 0u;
+  gather_keys<K>(row, pw, key);
+  count_gathered<K, G>(key, row, in_row, k0, ru_v, u, n1u, xbuf, red, lane, nd, n3);
   return true;
 }
 

@@ -286,3 +286,82 @@ def test_nan_is_refused():
     X[1, 2] = np.nan
     with pytest.raises(oracle.OracleError):
         oracle.allpairs(X)
+
+
+# ------------------------------------------------------------ permutation test
+
+
+def _mahonian(n):
+    """Number of permutations of n elements with k inversions, k = 0..n(n-1)/2
+    (the textbook recurrence: inserting the n-th element adds 0..n-1)."""
+    row = [1]
+    for size in range(2, n + 1):
+        nxt = [0] * (len(row) + size - 1)
+        for k, c in enumerate(row):
+            for j in range(size):
+                nxt[k + j] += c
+        row = nxt
+    return row
+
+
+def _s_by_definition(u, v):
+    u, v = [float(t) for t in u], [float(t) for t in v]
+    s = 0
+    for a in range(len(u)):
+        for b in range(a + 1, len(u)):
+            du = (u[a] > u[b]) - (u[a] < u[b])
+            dv = (v[a] > v[b]) - (v[a] < v[b])
+            s += du * dv
+    return s
+
+
+def test_perm_test_identity_permutations():
+    rng = np.random.default_rng(8)
+    X = np.round(rng.standard_normal((4, 30)), 1).astype(np.float32)
+    perms = np.tile(np.arange(30, dtype=np.uint16), (5, 1))
+    ys, xs = oracle.enumerate_pairs(4)
+    got = oracle.perm_test(X, perms, ys, xs)
+    assert (got["count"] == 5).all() and (got["p"] == 1.0).all()
+
+
+def test_perm_test_all_permutations_give_the_mahonian_tail():
+    # u in increasing order, v with distinct values: over all n! permutations
+    # of v's samples, S = n0 - 2 (inversions of the permuted v), and the
+    # number of permutations with k inversions is the Mahonian number M(n, k)
+    n = 6
+    n0 = n * (n - 1) // 2
+    M = _mahonian(n)
+    assert sum(M) == math.factorial(n)
+    perms = np.array(list(itertools.permutations(range(n))), dtype=np.uint16)
+    rng = np.random.default_rng(9)
+    for _ in range(6):
+        v = rng.permutation(n).astype(np.float32) + 0.5
+        X = np.vstack([np.arange(n, dtype=np.float32), v])
+        s_obs = abs(_s_by_definition(X[0], X[1]))
+        want = sum(c for k, c in enumerate(M) if abs(n0 - 2 * k) >= s_obs)
+        for method in ("gse", "brute"):
+            got = oracle.perm_test(X, perms, [0], [1], method)
+            assert got["count"][0] == want
+            assert got["p"][0] == (1 + want) / (len(perms) + 1)
+
+
+def test_perm_test_matches_the_definition_with_ties():
+    rng = np.random.default_rng(10)
+    n, B = 9, 40
+    X = rng.integers(0, 4, (5, n)).astype(np.float32)
+    X[4] = 1.0                                        # constant row: S = 0 always
+    perms = np.array([rng.permutation(n) for _ in range(B)], dtype=np.uint16)
+    ys, xs = oracle.enumerate_pairs(5)
+    got = oracle.perm_test(X, perms, ys, xs)
+    for i, (y, x) in enumerate(zip(ys, xs)):
+        s_obs = abs(_s_by_definition(X[y], X[x]))
+        want = sum(abs(_s_by_definition(X[y], X[x][p])) >= s_obs for p in perms)
+        assert got["count"][i] == want, (y, x)
+    assert (got["count"][xs == 4] == B).all()
+
+
+def test_perm_test_rejects_a_non_permutation():
+    X = np.arange(12, dtype=np.float32).reshape(2, 6)
+    bad = np.array([[0, 1, 2, 3, 4, 4]], dtype=np.uint16)
+    with pytest.raises(oracle.OracleError):
+        oracle.perm_test(X, bad, [0], [1])
