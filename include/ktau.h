@@ -236,6 +236,32 @@ int ktau_autotune(const int64_t* ns_host, int64_t count, const char* cache_path,
                   void* stream, int32_t* schemes_out_host, int32_t* q_out_host);
 
 /* ---------------------------------------------------------------------------
+ * Permutation test (Sec. 1: P-values of tau by permutation test, which needs
+ * many tau of every pair).
+ * ------------------------------------------------------------------------- */
+
+/* Device workspace bytes of ktau_perm_test (0 for a bad shape or B < 1). */
+size_t ktau_perm_workspace_size(int64_t m, int64_t n, int64_t B);
+
+/* For each strict pair (y, x) with job id J in [J_begin, J_end) (J_begin < 0:
+ * all jobs): |n_c - n_d| of row y against row x, and against row x with its
+ * samples permuted by each of the B permutations (x'[t] = x[perms[b*n + t]]);
+ * count_out[J - J_begin] (int64) = the number of permutations whose
+ * |n_c - n_d| is at least the observed one, p_out[J - J_begin] (double,
+ * may be NULL) = (1 + count) / (B + 1).  tau_B's denominator does not change
+ * under the permutations, so this is the two-sided permutation test of tau_B,
+ * decided in exact integers.
+ * perms_dev: uint16 [B][n], each row a permutation of 0..n-1 (checked on the
+ * device: a bad row latches KTAU_EINVAL in the workspace header and nothing
+ * is written; read it with ktau_status).  X_dev as in ktau_allpairs; the
+ * caller owns every buffer.  Errors returned at once: KTAU_EINVAL (null
+ * pointer, B < 1 or B >= 2^31, misaligned workspace), KTAU_ERANGE (n >
+ * KTAU_MAX_N or a bad job range), KTAU_ENOMEM (workspace too small). */
+int ktau_perm_test(const float* X_dev, int64_t m, int64_t n, const uint16_t* perms_dev,
+                   int64_t B, int64_t J_begin, int64_t J_end, int64_t* count_out_dev,
+                   double* p_out_dev, void* workspace_dev, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Query-vs-database search (Sec. 1: select the subject rows of a database
  * that are co-expressed with a query row, ranking query-subject pairs by
  * their score).  The score is tau_B; results are the k database rows of

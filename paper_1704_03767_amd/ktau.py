@@ -64,6 +64,8 @@ def _declare(lib):
         "ktau_scheme_name": ([i32], ctypes.c_char_p),
         "ktau_scheme_capacity": ([i32], i64),
         "ktau_default_scheme": ([i64], i32),
+        "ktau_perm_workspace_size": ([i64, i64, i64], sz),
+        "ktau_perm_test": ([p, i64, i64, p, i64, i64, i64, p, p, p, sz, p], i32),
     }
     for name, (args, res) in decl.items():
         f = getattr(lib, name)
@@ -268,6 +270,38 @@ def ktau_allpairs(X: torch.Tensor, out: dict | None = None, workspace: torch.Ten
         if st != KTAU_OK:
             raise KtauError(st, "ktau_allpairs")
     return out
+
+
+def ktau_perm_test(X: torch.Tensor, perms: torch.Tensor, J_begin: int = -1, J_end: int = -1,
+                   stream=None, check: bool = True) -> dict:
+    """Permutation test of every strict pair (or jobs [J_begin, J_end)):
+    perms is a CUDA uint16/int16 tensor B x n, each row a permutation of the
+    samples applied to the pair's second row.  Returns device tensors
+    count (int64: permutations with |n_c - n_d| at least the observed) and
+    p (float64: (1 + count) / (B + 1)), indexed by job id - J_begin."""
+    X = _as_matrix(X)
+    m, n = X.shape
+    if perms.dim() != 2 or perms.shape[1] != n or not perms.is_contiguous() or \
+            perms.element_size() != 2 or perms.device != X.device:
+        raise KtauError(KTAU_EINVAL, "ktau_perm_test: perms must be a contiguous B x n "
+                                     "16-bit tensor on the device of X")
+    B = perms.shape[0]
+    P = m * (m - 1) // 2
+    if J_begin < 0:
+        J_begin, J_end = 0, P
+    size = int(lib().ktau_perm_workspace_size(m, n, B))
+    if size == 0:
+        raise KtauError(KTAU_EINVAL if n <= KTAU_MAX_N else KTAU_ERANGE, "perm workspace size")
+    ws = torch.empty(size, dtype=torch.uint8, device=X.device)
+    count = torch.empty(J_end - J_begin, dtype=torch.int64, device=X.device)
+    p = torch.empty(J_end - J_begin, dtype=torch.float64, device=X.device)
+    _check(lib().ktau_perm_test(_ptr(X), m, n, _ptr(perms), B, J_begin, J_end, _ptr(count),
+                                _ptr(p), _ptr(ws), size, _stream(stream)), "ktau_perm_test")
+    if check:
+        st = ktau_status(ws, stream)
+        if st != KTAU_OK:
+            raise KtauError(st, "ktau_perm_test")
+    return {"count": count, "p": p}
 
 
 def ktau_allpairs_range(X: torch.Tensor, J_begin: int, J_end: int, out: dict | None = None,

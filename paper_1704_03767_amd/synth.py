@@ -91,6 +91,13 @@ def samples_matrix(m: int = 353, n: int = 17941, seed: int = 6, groups: int = 4,
     return X.astype(np.float32)
 
 
+def permutations(B: int, n: int, seed: int) -> np.ndarray:
+    """B independent uniform permutations of 0..n-1 (rows, uint16) for the
+    permutation test."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.permutation(n) for _ in range(B)]).astype(np.uint16)
+
+
 def config_matrix(cfg: int, seed: int | None = None) -> np.ndarray:
     """The single-matrix workloads 1-3."""
     seed = DEFAULT_SEEDS[cfg] if seed is None else seed

@@ -74,6 +74,19 @@ def test_host_side_argument_errors():
                        None) == K.KTAU_EINVAL
     assert L.ktau_rank(fake, 3, 20000, None, None, None, None, fake, fake, need - 1,
                        None) == K.KTAU_ENOMEM
+    # permutation test: host-side argument checks
+    need = L.ktau_perm_workspace_size(10, 100, 4)
+    assert need > L.ktau_allpairs_workspace_size(10, 100) and L.ktau_perm_workspace_size(10, 100, 0) == 0
+    assert L.ktau_perm_test(fake, 10, 100, None, 4, -1, -1, fake, None, fake, need,
+                            None) == K.KTAU_EINVAL
+    assert L.ktau_perm_test(fake, 10, 100, fake, 0, -1, -1, fake, None, fake, need,
+                            None) == K.KTAU_EINVAL
+    assert L.ktau_perm_test(fake, 10, 100, fake, 4, -1, -1, fake, None, fake, need - 1,
+                            None) == K.KTAU_ENOMEM
+    assert L.ktau_perm_test(fake, 10, 100, fake, 4, 3, 46, fake, None, fake, need,
+                            None) == K.KTAU_ERANGE
+    assert L.ktau_perm_test(fake, 10, K.KTAU_MAX_N + 1, fake, 4, -1, -1, fake, None, fake,
+                            need, None) == K.KTAU_ERANGE
     assert L.ktau_pair_to_job(10, 3, 3) == -1
     assert L.ktau_pair_to_job(10, 4, 3) == -1
     assert L.ktau_pair_to_job(10, 3, 10) == -1
