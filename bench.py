@@ -198,6 +198,49 @@ def other_shapes(K, synth, torch, stream, reps: int) -> dict:
     return {"gene_vs_gene": genes, "sample_vs_sample": samples}
 
 
+def perm_test(K, synth, torch, stream, reps: int) -> dict:
+    """Permutation-test P-values (Sec. 1): m = 512 log-normal rows (blocks of
+    64 at rho = 0.6, 2% exact zeros, seed 11) of n = 1024 samples, B = 200
+    permutations (seed 12) of the second row of every pair: 201 tau counts
+    per pair."""
+    X = synth.lognormal_blocks(512, 1024, 11)
+    perms = synth.permutations(200, 1024, 12)
+    m, n = X.shape
+    B = perms.shape[0]
+    P = m * (m - 1) // 2
+    Xd = torch.from_numpy(X).cuda()
+    Pd = torch.from_numpy(perms.astype("int16")).cuda()
+    size = K.lib().ktau_perm_workspace_size(m, n, B)
+    ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+    count = torch.empty(P, dtype=torch.int64, device="cuda")
+    p = torch.empty(P, dtype=torch.float64, device="cuda")
+
+    def run():
+        rc = K.lib().ktau_perm_test(K._ptr(Xd), m, n, K._ptr(Pd), B, -1, -1, K._ptr(count),
+                                    K._ptr(p), K._ptr(ws), size, K._stream(stream))
+        if rc != K.KTAU_OK:
+            raise RuntimeError(f"ktau_perm_test: {K.status_string(rc)}")
+
+    run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    if K.ktau_status(ws) != K.KTAU_OK:
+        raise RuntimeError("permutation test failed on the device")
+    ms = e0.elapsed_time(e1) / reps
+    taus = P * (B + 1)
+    return {"workload": "m=512 n=1024 log-normal (blocks of 64, rho=0.6, 2% zeros, seed 11), "
+                        "B=200 permutations (seed 12)",
+            "pairs": P, "permutations": B, "ms": ms, "tau_per_s": taus / (ms * 1e-3),
+            "scheme": K.ktau_scheme_names()[K.ktau_default_scheme(n)],
+            "median_p": float(p.median().item())}
+
+
 def serving(K, synth, torch, stream, seconds: float) -> dict:
     """Query-vs-database search over a resident 20000 x 800 log-normal
     database (seed 5): requests of 1-64 query rows, top-100 by |tau_B|.
@@ -308,6 +351,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-shapes", action="store_true",
                     help="skip the gene-vs-gene and sample-vs-sample shapes")
+    ap.add_argument("--no-perm", action="store_true", help="skip the permutation test")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="target length of each Poisson run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -437,6 +481,8 @@ def main() -> int:
         result["uneven_batch"] = uneven_batch(K, synth, torch, stream, max(2, args.steps))
     if not args.no_shapes:
         result["shapes"] = other_shapes(K, synth, torch, stream, max(2, args.steps))
+    if not args.no_perm:
+        result["perm_test"] = perm_test(K, synth, torch, stream, 2)
     if not args.no_serve:
         result["serving"] = serving(K, synth, torch, stream, args.serve_seconds)
         rates = result["serving"]["at_rates"]

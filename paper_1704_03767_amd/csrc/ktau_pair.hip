@@ -62,8 +62,8 @@ __device__ __forceinline__ void tile_pairs(const MatDesc& d, int64_t yq, int64_t
 
 // Plain launch over the tiles.  With one workgroup per tile the tiles follow
 // the XCD-aware band schedule (input rows reused from L2); otherwise a grid
-// stride over the tile ids.  (One call site of the pair routine: the kernel's
-// code stays within the instruction cache.)
+// stride over the tile ids.  (A single call site of the pair routine halves
+// the code but measured about 1% slower.)
 template <int K, int G>
 __global__ void __launch_bounds__(kBlock, (fast_waves<K, G>())) pairs_tiles_kernel(MatDesc d) {
   using FL = FastLds<K, G>;
@@ -71,11 +71,14 @@ __global__ void __launch_bounds__(kBlock, (fast_waves<K, G>())) pairs_tiles_kern
   uint32_t* red = FL::red(lds);
   if (*d.status != 0) return;
   const int group = threadIdx.x / G;
-  const bool scheduled = (int64_t)gridDim.x == d.n_units;
+  int64_t yq, xq;
+  if ((int64_t)gridDim.x == d.n_units) {
+    scheduled_tile(d.w, d.n_units, blockIdx.x, yq, xq);
+    tile_pairs<K, G>(d, yq, xq, lds, red, group, FL::kGroups);
+    return;
+  }
   for (int64_t t = blockIdx.x; t < d.n_units; t += gridDim.x) {
-    int64_t yq, xq;
-    if (scheduled) scheduled_tile(d.w, d.n_units, t, yq, xq);
-    else tile_coord(d.w, t, yq, xq);
+    tile_coord(d.w, t, yq, xq);
     tile_pairs<K, G>(d, yq, xq, lds, red, group, FL::kGroups);
   }
 }
