@@ -41,14 +41,22 @@ def merge_steps(n: int) -> int:
     return n * math.ceil(math.log2(n))
 
 
+# The sources the all-pairs kernel is built from: a committed counter summary
+# holds for the kernel only while these are unchanged.
+PAIR_KERNEL_SOURCES = ("paper_1704_03767_amd/csrc/ktau_pair.hip",
+                       "paper_1704_03767_amd/csrc/ktau_pairdev.h",
+                       "paper_1704_03767_amd/csrc/ktau_bitonic.h",
+                       "paper_1704_03767_amd/csrc/ktau_internal.h",
+                       "paper_1704_03767_amd/csrc/ktau_order.h",
+                       "include/ktau.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1704_03767_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for rel in PAIR_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

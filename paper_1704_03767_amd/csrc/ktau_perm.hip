@@ -11,7 +11,10 @@
 // LDS once, y's sorted order is loaded once, and each permutation rebuilds a
 // second LDS row (slot t gets rank_x[pi[t]]) before the usual gather, direct
 // in-run tie count and network count.  Every pair takes the direct tie count
-// (no composite pass), which is exact for any ties.
+// (no composite pass), which is exact for any ties; its cost follows the
+// tie term of the row whose order is used, so when x has fewer ties the
+// roles turn: permuting both rows' samples by pi^-1 leaves n_c - n_d alone,
+// so |n_c - n_d| of (y, x o pi) is that of (x, y o pi^-1).
 #include "ktau_pairdev.h"
 
 namespace ktau {
@@ -29,11 +32,13 @@ struct PermLds {
 };
 
 // Checks that each of the B rows of perms (n entries, row stride n) is a
-// permutation of 0..n-1 (else latches KTAU_EINVAL) and writes it as byte
-// offsets into a rank row (2 pi[t]) to pad, row stride ld, identity past n.
+// permutation of 0..n-1 (else latches KTAU_EINVAL) and writes it, and its
+// inverse, as byte offsets into a rank row (2 pi[t], 2 pi^-1[t]) to pad and
+// inv, row stride ld, identity past n.
 __global__ void __launch_bounds__(256)
 perm_check_kernel(const uint16_t* __restrict__ perms, int n, int64_t ld,
-                  uint16_t* __restrict__ pad, int32_t* __restrict__ status) {
+                  uint16_t* __restrict__ pad, uint16_t* __restrict__ inv,
+                  int32_t* __restrict__ status) {
   extern __shared__ uint32_t seen[];   // n bits
   const int64_t b = blockIdx.x;
   const int words = (n + 31) / 32;
@@ -50,14 +55,19 @@ perm_check_kernel(const uint16_t* __restrict__ perms, int n, int64_t ld,
     const uint32_t bit = 1u << (v & 31u);
     if (atomicOr(&seen[v >> 5], bit) & bit) bad = true;
     pad[b * ld + t] = (uint16_t)(2 * v);
+    inv[b * ld + v] = (uint16_t)(2 * t);   // a permutation writes every slot once
   }
-  for (int64_t t = n + threadIdx.x; t < ld; t += blockDim.x) pad[b * ld + t] = (uint16_t)(2 * t);
+  for (int64_t t = n + threadIdx.x; t < ld; t += blockDim.x) {
+    pad[b * ld + t] = (uint16_t)(2 * t);
+    inv[b * ld + t] = (uint16_t)(2 * t);
+  }
   if (__syncthreads_or(bad) && threadIdx.x == 0) atomicExch(status, KTAU_EINVAL);
 }
 
 struct PermDesc {
   RankView rv;
   const uint16_t* pad;     // [B][ld] permutations as byte offsets
+  const uint16_t* inv;     // [B][ld] their inverses
   int64_t B;
   int64_t* count_out;      // [J_end - J_begin]
   double* p_out;           // [J_end - J_begin] or NULL
@@ -77,18 +87,29 @@ __device__ __forceinline__ int64_t pair_perm(const PermDesc& d, int64_t y, int64
   constexpr int KV = K / 2;
   const RankView& rv = d.rv;
   const int64_t ld = rv.ld;
+  const int64_t n = d.n;
+  const int64_t n0 = n * (n - 1) / 2;
+  const int64_t n1y = rv.n1[y], n1x = rv.n1[x];
+  // u: the row with fewer ties, whose order is used; the other row's samples
+  // are permuted (by pi if that is x, by pi^-1 if it is y)
+  const bool swap = n1x < n1y;
+  const int64_t u = swap ? x : y, v = swap ? y : x;
+  const int64_t n1u = swap ? n1x : n1y;
+  const uint16_t* table = swap ? d.inv : d.pad;
+  // a constant u: every n_c - n_d is 0, every permutation counts
+  if (n1u == n0) return d.B;
   const int k0 = Net::logical_lane(lane) * K;
   const bool in_row = k0 + K <= ld;   // ld is a multiple of 128
-  uint16_t* row_x = (uint16_t*)lds;
+  uint16_t* row_v = (uint16_t*)lds;
   uint16_t* row_p = (uint16_t*)(lds + PL::kRowWords);
   uint32_t* xbuf = lds + 2 * PL::kRowWords;
-  // x's rank row (lanes past the row: padding keys), y's order (byte offsets)
+  // v's rank row (lanes past the row: padding keys), u's order (byte offsets)
   uint32_t pw[KV];
   {
     uint32_t w[KV];
     if (in_row) {
-      load_words<K>(rv.rank + x * ld + k0, w);
-      load_words<K>(rv.perm + y * ld + k0, pw);
+      load_words<K>(rv.rank + v * ld + k0, w);
+      load_words<K>(rv.perm + u * ld + k0, pw);
     } else {
 #pragma unroll
       for (int i = 0; i < KV; ++i) {
@@ -96,19 +117,18 @@ __device__ __forceinline__ int64_t pair_perm(const PermDesc& d, int64_t y, int64
         pw[i] = (uint32_t)(2 * (k0 + 2 * i)) | ((uint32_t)(2 * (k0 + 2 * i + 1)) << 16);
       }
     }
-    store_words<K>(row_x + k0, w);
+    store_words<K>(row_v + k0, w);
   }
-  const int64_t n = d.n;
-  const int64_t n1y = rv.n1[y], n1x = rv.n1[x];
-  const int64_t base = n * (n - 1) / 2 - n1y - n1x;   // S = base + n3 - 2 n_d
-  const char* rowb = (const char*)row_x;
+  const int64_t base = n0 - n1y - n1x;   // S = base + n3 - 2 n_d
+  const char* rowb = (const char*)row_v;
   int64_t s_obs = 0, count = 0;
   for (int64_t b = -1; b < d.B; ++b) {
-    group_sync<G>();   // the previous pass is done with row_p (and row_x is staged)
-    // row_p[t] = rank_x[pi_b[t]] for this lane's slots (b < 0: the identity)
+    group_sync<G>();   // the previous pass is done with row_p (and row_v is staged)
+    // row_p[t] = rank_v[sigma_b[t]] for this lane's slots (sigma = pi, or
+    // pi^-1 when the roles turned; b < 0: the identity)
     uint32_t pi[KV];
     if (b >= 0 && in_row) {
-      load_words<K>(d.pad + b * ld + k0, pi);
+      load_words<K>(table + b * ld + k0, pi);
     } else {
 #pragma unroll
       for (int i = 0; i < KV; ++i)
@@ -124,7 +144,7 @@ __device__ __forceinline__ int64_t pair_perm(const PermDesc& d, int64_t y, int64
     u16x2 key[KV];
     gather_keys<K>(row_p, pw, key);
     uint32_t nd, n3;
-    count_gathered<K, G>(key, row_p, in_row, k0, rv, y, n1y, xbuf, red, lane, nd, n3);
+    count_gathered<K, G>(key, row_p, in_row, k0, rv, u, n1u, xbuf, red, lane, nd, n3);
     int64_t s = base + (int64_t)n3 - 2 * (int64_t)nd;
     s = s < 0 ? -s : s;
     if (b < 0) s_obs = s;
@@ -186,6 +206,10 @@ size_t perm_pad_offset(int64_t m, int64_t n) {
   return (size_t)round_up((int64_t)ws_layout(m, n).total, (int64_t)kAlign);
 }
 
+size_t perm_table_bytes(int64_t n, int64_t B) {
+  return (size_t)round_up(B * row_ld(n) * 2, (int64_t)kAlign);
+}
+
 }  // namespace
 }  // namespace ktau
 
@@ -195,7 +219,7 @@ extern "C" {
 
 size_t ktau_perm_workspace_size(int64_t m, int64_t n, int64_t B) {
   if (check_shape(m, n) != KTAU_OK || B < 1) return 0;
-  return perm_pad_offset(m, n) + (size_t)round_up(B * row_ld(n) * 2, (int64_t)kAlign);
+  return perm_pad_offset(m, n) + 2 * perm_table_bytes(n, B);
 }
 
 int ktau_perm_test(const float* X, int64_t m, int64_t n, const uint16_t* perms, int64_t B,
@@ -218,15 +242,17 @@ int ktau_perm_test(const float* X, int64_t m, int64_t n, const uint16_t* perms, 
   if ((rc = prepass_ws(X, m, n, ws, nullptr, nullptr, s)) != KTAU_OK) return rc;
   const WsLayout L = ws_layout(m, n);
   uint16_t* pad = (uint16_t*)((char*)ws + perm_pad_offset(m, n));
+  uint16_t* inv = (uint16_t*)((char*)pad + perm_table_bytes(n, B));
   const size_t bits = (size_t)((n + 31) / 32) * sizeof(uint32_t);
   hipLaunchKernelGGL(perm_check_kernel, dim3((unsigned)B), dim3(256), bits, s, perms, (int)n,
-                     L.ld, pad, status);
+                     L.ld, pad, inv, status);
   if (hipGetLastError() != hipSuccess) return KTAU_EDEVICE;
   if (J_end == J_begin) return KTAU_OK;
   const MatDesc md = matdesc(ws, m, n, ktau_pair_out{}, 0, 8, J_begin, J_end, status);
   PermDesc d;
   d.rv = md.rv;
   d.pad = pad;
+  d.inv = inv;
   d.B = B;
   d.count_out = count_out;
   d.p_out = p_out;

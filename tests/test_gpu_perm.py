@@ -70,6 +70,22 @@ def test_identity_permutations_and_ranges():
     assert np.array_equal(full["count"][17:150], _want(X, perms, np.arange(17, 150))["count"])
 
 
+def test_tied_and_constant_rows_take_the_lighter_order():
+    # heavily tied second rows make the kernel permute the first row by the
+    # inverse permutations instead; two constant rows give count = B at once
+    rng = np.random.default_rng(68)
+    n = 900
+    X = np.round(rng.standard_normal((10, n)), 2).astype(np.float32)
+    X[1::3] = rng.integers(0, 2, (3, n))            # binary rows after lighter ones
+    X[8] = 4.0
+    X[9] = -1.0
+    perms = synth.permutations(16, n, 69)
+    got = _run(X, perms)
+    want = _want(X, perms)
+    assert np.array_equal(got["count"], want["count"])
+    assert got["count"][K.ktau_pair_to_job(10, 8, 9)] == 16
+
+
 def test_a_bad_permutation_is_reported():
     X = _tied_matrix(8, 100, 65)
     perms = synth.permutations(3, 100, 66)
