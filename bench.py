@@ -80,6 +80,17 @@ def read_traffic(kernel_tag: str, src_hash: str):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(X, seconds: float, seed: int = 99) -> dict:
     """The oracle (sorting kernel, all host threads) on a seeded sample of pairs."""
     import numpy as np
@@ -107,8 +118,8 @@ def cpu_baseline(X, seconds: float, seed: int = 99) -> dict:
         batch = int(min(20_000_000, max(threads * 64, 1.1 * left * count / max(dt, 1e-6))))
     return {"value": count / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} seeded random strict pairs of the same matrix, "
-                      f"sorting-kernel routine, {dt:.1f} s on {threads} threads "
-                      f"({platform.processor() or platform.machine()})"}
+                      f"sorting-kernel routine, {dt:.1f} s on {threads} threads",
+            "cpu": cpu_model(), "nproc": os.cpu_count()}
 
 
 def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
@@ -417,8 +428,10 @@ def main() -> int:
     if st != K.KTAU_OK:
         raise RuntimeError(f"device status {st}")
     ms_plain = (t1 - t0) * 1e3 / args.steps
-    prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
-    pair_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+    prep_all = [e[0].elapsed_time(e[1]) for e in events]
+    pair_all = [e[1].elapsed_time(e[2]) for e in events]
+    prep_ms = float(np.mean(prep_all))
+    pair_ms = float(np.mean(pair_all))
 
     # the batched form of the same workload: a one-matrix plan (persistent
     # kernel, autotuned scheme, hipGraph), writing the same output arrays
@@ -430,15 +443,23 @@ def main() -> int:
         torch.cuda.synchronize()
         if plan.status(stream) != K.KTAU_OK:
             raise RuntimeError("batched warm-up failed")
+        bev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)]
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for i in range(args.steps):
+            bev[i][0].record(stream)
             plan.run(stream)
+            bev[i][1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if plan.status(stream) != K.KTAU_OK:
             raise RuntimeError("batched run failed")
         ms_batched = (t1 - t0) * 1e3 / args.steps
+        step_all = [e[0].elapsed_time(e[1]) for e in bev]
         batched = {"ms_per_step": ms_batched, "pairs_per_s": P / (ms_batched * 1e-3),
+                   "step_ms_median": float(np.median(step_all)),
+                   "step_ms_min": float(np.min(step_all)),
                    "scheme": plan.plan(0)[0], "q": plan.plan(0)[1]}
         plan.close()
     ms_step = ms_plain if batched is None else batched["ms_per_step"]
@@ -471,7 +492,10 @@ def main() -> int:
         },
         "plain": {"ms_per_step": ms_plain, "pairs_per_s": P / (ms_plain * 1e-3),
                   "scheme": K.ktau_scheme_names()[scheme], "q": args.q or 8,
-                  "prepass_ms": prep_ms, "pair_kernel_ms": pair_ms},
+                  "prepass_ms": prep_ms, "pair_kernel_ms": pair_ms,
+                  "pair_kernel_ms_median": float(np.median(pair_all)),
+                  "pair_kernel_ms_min": float(np.min(pair_all)),
+                  "prepass_ms_median": float(np.median(prep_all))},
         "batched": batched,
         "roofline": {
             "bound": "alu",
