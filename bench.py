@@ -31,6 +31,9 @@ CLOCK_HZ = 2.4e9
 # Integer VALU: 4 SIMDs per CU, each retiring one 64-lane wave instruction
 # every 4 cycles = 64 int32 lane-ops per CU per cycle.
 INT_VALU_OPS = CUS * 64 * CLOCK_HZ           # 3.93e13 lane-ops/s
+# LDS reference width: 128 bytes per cycle per CU (the CDNA3 figure; the
+# probe measures what gfx950 reaches).
+LDS_BYTES_PER_S = CUS * 128 * CLOCK_HZ       # 7.86e13 B/s
 # The paper's VSE kernel on one Xeon Phi 5110P for its 17,941 x 353 dataset
 # (Table 4: 296 s), as strict pairs per second: context, not a target.
 PAPER_PHI_DS3526 = 17941 * 17940 / 2 / 296.0
@@ -41,14 +44,14 @@ def merge_steps(n: int) -> int:
     return n * math.ceil(math.log2(n))
 
 
-# The sources the all-pairs kernel is built from: a committed counter summary
-# holds for the kernel only while these are unchanged.
+# The sources the all-pairs kernel is built from (the public header adds only
+# declarations and status codes): a committed counter summary holds for the
+# kernel only while these are unchanged.
 PAIR_KERNEL_SOURCES = ("paper_1704_03767_amd/csrc/ktau_pair.hip",
                        "paper_1704_03767_amd/csrc/ktau_pairdev.h",
                        "paper_1704_03767_amd/csrc/ktau_bitonic.h",
                        "paper_1704_03767_amd/csrc/ktau_internal.h",
-                       "paper_1704_03767_amd/csrc/ktau_order.h",
-                       "include/ktau.h")
+                       "paper_1704_03767_amd/csrc/ktau_order.h")
 
 
 def kernel_source_hash() -> str:
@@ -464,6 +467,8 @@ def main() -> int:
         plan.close()
     ms_step = ms_plain if batched is None else batched["ms_per_step"]
 
+    # the library's probes measure the int32 VALU and LDS peaks on this GPU
+    probes = K.probe_peaks(stream=stream)
     steps_per_pair = merge_steps(n)
     ops_per_launch = P * steps_per_pair
     achieved = ops_per_launch / (pair_ms * 1e-3)
@@ -497,6 +502,10 @@ def main() -> int:
                   "pair_kernel_ms_min": float(np.min(pair_all)),
                   "prepass_ms_median": float(np.median(prep_all))},
         "batched": batched,
+        "probes": {"valu_lane_ops_per_s": probes["valu_lane_ops_per_s"],
+                   "valu_published": INT_VALU_OPS,
+                   "lds_bytes_per_s": probes["lds_bytes_per_s"],
+                   "lds_reference_128B_per_clk": LDS_BYTES_PER_S},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -504,6 +513,8 @@ def main() -> int:
             "unit": "TOP/s",
             "frac": achieved / INT_VALU_OPS,
             "traffic": traffic,
+            "measured_peak": probes["valu_lane_ops_per_s"] / 1e12,
+            "frac_of_measured": achieved / probes["valu_lane_ops_per_s"],
             "kernel": kernel_tag,
             "ops_per_pair": steps_per_pair,
             "source_hash": src_hash,

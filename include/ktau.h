@@ -374,6 +374,25 @@ size_t ktau_server_launch_bytes(const ktau_server* server, int64_t nq, int64_t k
  * server. */
 void ktau_server_destroy(ktau_server* server);
 
+/* ---------------------------------------------------------------------------
+ * Diagnostics: kernels with a known amount of work per launch, for the
+ * callers' own measurement of the peaks the rooflines are quoted against.
+ * ------------------------------------------------------------------------- */
+
+/* Threads per workgroup of the probes, int32 adds per thread per iteration of
+ * the VALU probe, LDS bytes read per thread per iteration of the LDS probe. */
+int ktau_probe_threads(void);
+int ktau_probe_valu_ops_per_iter(void);
+int ktau_probe_lds_bytes_per_iter(void);
+
+/* Launch `blocks` workgroups of the VALU probe (int32 adds, 16 independent
+ * chains per lane) or the LDS probe (conflict-free 16-byte reads of a 64 KB
+ * workgroup buffer), `iters` iterations each, on `stream`; out_dev receives
+ * one uint32 per thread (blocks * ktau_probe_threads()).  KTAU_EINVAL for a
+ * null out_dev, blocks < 1 or iters < 1. */
+int ktau_probe_valu(uint32_t* out_dev, int64_t blocks, int iters, void* stream);
+int ktau_probe_lds(uint32_t* out_dev, int64_t blocks, int iters, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

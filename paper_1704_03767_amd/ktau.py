@@ -65,6 +65,11 @@ def _declare(lib):
         "ktau_scheme_capacity": ([i32], i64),
         "ktau_default_scheme": ([i64], i32),
         "ktau_perm_workspace_size": ([i64, i64, i64], sz),
+        "ktau_probe_threads": ([], i32),
+        "ktau_probe_valu_ops_per_iter": ([], i32),
+        "ktau_probe_lds_bytes_per_iter": ([], i32),
+        "ktau_probe_valu": ([p, i64, i32, p], i32),
+        "ktau_probe_lds": ([p, i64, i32, p], i32),
         "ktau_perm_test": ([p, i64, i64, p, i64, i64, i64, p, p, p, sz, p], i32),
     }
     for name, (args, res) in decl.items():
@@ -430,3 +435,38 @@ def ktau_autotune(ns, cache_path: str | None = None, stream=None) -> list[tuple[
                            _stream(stream), sch, qs), "ktau_autotune")
     names = ktau_scheme_names()
     return [(names[s], q) for s, q in zip(sch, qs)]
+
+
+# ------------------------------------------------------------ diagnostics
+
+
+def probe_peaks(blocks: int = 2048, valu_iters: int = 20000, lds_iters: int = 2000,
+                stream=None) -> dict:
+    """Measured int32 VALU lane-operations/s and LDS bytes/s from the
+    library's probe kernels (each timed with events on `stream`, best of
+    three launches after a warm-up)."""
+    L = lib()
+    threads = L.ktau_probe_threads()
+    out = torch.empty(blocks * threads, dtype=torch.int32, device="cuda")
+    st = stream or torch.cuda.current_stream()
+
+    def best(fn, iters):
+        _check(fn(_ptr(out), blocks, iters, _stream(st)), "probe")
+        ms = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            _check(fn(_ptr(out), blocks, iters, _stream(st)), "probe")
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return min(ms)
+
+    v_ms = best(L.ktau_probe_valu, valu_iters)
+    l_ms = best(L.ktau_probe_lds, lds_iters)
+    ops = blocks * threads * L.ktau_probe_valu_ops_per_iter() * valu_iters
+    byt = blocks * threads * L.ktau_probe_lds_bytes_per_iter() * lds_iters
+    return {"valu_lane_ops_per_s": ops / (v_ms * 1e-3), "lds_bytes_per_s": byt / (l_ms * 1e-3),
+            "valu_ms": v_ms, "lds_ms": l_ms}
+

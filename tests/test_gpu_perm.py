@@ -99,3 +99,4 @@ def test_a_bad_permutation_is_reported():
     # a good call on a fresh workspace afterwards
     good = synth.permutations(3, 100, 67)
     assert np.array_equal(_run(X, good)["count"], _want(X, good)["count"])
+
