@@ -249,6 +249,16 @@ def test_nan_input_is_reported():
     _check_full(synth.config_matrix(1))
 
 
+@pytest.mark.parametrize("col", [3, 16384, 19999])
+def test_nan_in_a_long_row_is_reported(col):
+    # rows over 16384 samples are sorted in two halves: a NaN in either half
+    X = synth.samples_matrix(4, 20000, 6)
+    X[2, col] = np.nan
+    with pytest.raises(K.KtauError) as e:
+        _gpu_allpairs(X)
+    assert e.value.status == K.KTAU_ENAN
+
+
 # ------------------------------------------------------------ full-size workloads
 
 

@@ -86,6 +86,14 @@ def test_tied_and_constant_rows_take_the_lighter_order():
     assert got["count"][K.ktau_pair_to_job(10, 8, 9)] == 16
 
 
+def test_nan_is_reported():
+    X = _tied_matrix(6, 200, 72)
+    X[4, 17] = np.nan
+    with pytest.raises(K.KtauError) as e:
+        _run(X, synth.permutations(3, 200, 73))
+    assert e.value.status == K.KTAU_ENAN
+
+
 def test_a_bad_permutation_is_reported():
     X = _tied_matrix(8, 100, 65)
     perms = synth.permutations(3, 100, 66)
