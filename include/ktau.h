@@ -17,8 +17,9 @@
  *
  * Counts come from the sorting method of Sec. 3.2: samples ordered by u (a
  * per-row rank pre-pass done once per row, Sec. 3), v permuted into that order,
- * discordant pairs counted as strict inversions by merge sort (Algorithm 2),
- * tie runs scanned.  Pairs are numbered by the job-id bijection of Sec. 4.1
+ * discordant pairs counted as strict inversions (Step 3; Algorithm 2 counts
+ * them by merge sort, the kernels here by a bitonic network that yields the
+ * same count), tie runs scanned.  Pairs are numbered by the job-id bijection of Sec. 4.1
  * (Eq. 4-10) restricted to the strict upper triangle: row-major, y < x,
  *     J(y, x) = F(y) + (x - y - 1),  F(y) = y (2(m-1) - y + 1) / 2,
  * J in [0, m(m-1)/2).  Work is spread in q x q tiles numbered by Eq. 11-14.
@@ -152,15 +153,17 @@ int ktau_pairs(int64_t m, int64_t n, int64_t J_begin, int64_t J_end,
                int scheme, int q, void* stream);
 
 /* Waits for `stream`, then returns the status latched in a workspace by the
- * last call that used it (KTAU_ENAN if the input held a NaN, else KTAU_OK),
- * and clears it. */
+ * last call that used it (KTAU_ENAN if the input held a NaN, KTAU_EINVAL if a
+ * permutation given to ktau_perm_test was not one, else KTAU_OK), and clears
+ * it. */
 int ktau_status(void* workspace_dev, void* stream);
 
 
 /* ---------------------------------------------------------------------------
  * Per-pair schemes and an explicit-scheme entry point (for tuning and tests).
- * A scheme is a group size (one 64-lane wave, or a 256-lane workgroup) and a
- * number K of keys per lane; it handles n <= lanes * K.
+ * A scheme is a group size (8, 16 or 32 lanes of a wave, a whole 64-lane
+ * wave, or a 256-lane workgroup) and a number K of keys per lane; it handles
+ * n <= lanes * K.
  * ------------------------------------------------------------------------- */
 
 int ktau_scheme_count(void);
@@ -176,10 +179,11 @@ int ktau_allpairs_ex(const float* X_dev, int64_t m, int64_t n, int64_t J_begin,
                      size_t ws_bytes, int scheme, int q, void* stream);
 /* ---------------------------------------------------------------------------
  * Batched all-pairs: many independent matrices of uneven (m, n) in one
- * persistent launch.  Workgroups take q x q tiles (Sec. 4.2) of any matrix
- * from one atomic counter -- the shared-counter distribution that Sec. 4.1
- * names for jobs of varied cost -- so small matrices do not leave the device
- * idle.  The launch sequence (status clear, one pre-pass over all rows, the
+ * persistent launch per scheme class.  Workgroups take q x q tiles (Sec. 4.2)
+ * of any matrix of the class from atomic counters -- the shared-counter
+ * distribution that Sec. 4.1 names for jobs of varied cost; one counter per
+ * XCD's stretch of the tiles, with stealing between stretches -- so small
+ * matrices do not leave the device idle.  The launch sequence (status clear, one pre-pass over all rows, the
  * persistent pair kernel, the heavy-tie composite pass) is captured in a
  * hipGraph on the first ktau_batch_run and replayed afterwards.
  * ------------------------------------------------------------------------- */
@@ -275,7 +279,7 @@ int ktau_perm_test(const float* X_dev, int64_t m, int64_t n, const uint16_t* per
 typedef struct ktau_db ktau_db;   /* opaque: ranked database resident in HBM */
 
 /* Ranks the m x n database X_dev once into library-owned device memory
- * (about 6 m ceil64(n) bytes); X_dev may be freed afterwards.  Synchronises
+ * (about 10 m ceil128(n) bytes); X_dev may be freed afterwards.  Synchronises
  * `stream`; KTAU_ENAN if X_dev holds a NaN. */
 int ktau_db_create(const float* X_dev, int64_t m, int64_t n, void* stream,
                    ktau_db** db_out);
