@@ -86,19 +86,52 @@ __device__ __forceinline__ uint64_t tau_key(double t) {
   return (uint64_t)__double_as_longlong(fabs(t)) + 1;
 }
 
-// Sorts `cnt` (power of two, <= kChunk) items of LDS into `before` order.
-__device__ void bitonic_items(TopItem* s, int cnt) {
-  for (int size = 2; size <= cnt; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool up = (i & size) == 0;
-          const TopItem a = s[i], b = s[j];
-          const bool swap = up ? before(b, a) : before(a, b);
-          if (swap) {
-            s[i] = b;
-            s[j] = a;
+// Compare-exchange stages of width `stride` down to 1 over the first `cnt`
+// items: the pair (i, i ^ stride) is put in `before` order, reversed where
+// bit `dir` of i is set (dir = 0: never).
+__device__ void bitonic_stages(TopItem* s, int cnt, int stride, int dir) {
+  for (; stride > 0; stride >>= 1) {
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+      const int j = i ^ stride;
+      if (j > i) {
+        const bool up = dir == 0 || (i & dir) == 0;
+        const TopItem a = s[i], b = s[j];
+        if (up ? before(b, a) : before(a, b)) {
+          s[i] = b;
+          s[j] = a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The k2 best of `cnt` items of LDS (both powers of two, k2 <= cnt), in
+// `before` order, in s[0 .. k2): every block of k2 items is sorted, then
+// blocks are merged pairwise keeping the better half -- the better of A[i]
+// and B[k2 - 1 - i] over i is the k2 best of A and B, as a bitonic sequence
+// that log2(k2) more stages sort -- until one block is left.
+__device__ void topk_items(TopItem* s, int cnt, int k2) {
+  for (int size = 2; size <= k2; size <<= 1) bitonic_stages(s, cnt, size >> 1, size < k2 ? size : 0);
+  for (int step = k2; step < cnt; step <<= 1) {
+    // blocks at multiples of step: block b keeps the best of b and b + step
+    for (int i = threadIdx.x; i < cnt / 2; i += blockDim.x) {
+      const int b = (i / k2) * 2 * step, t = i % k2;
+      if (b + step < cnt) {
+        const TopItem a = s[b + t], c = s[b + step + k2 - 1 - t];
+        if (before(c, a)) s[b + t] = c;
+      }
+    }
+    __syncthreads();
+    for (int stride = k2 >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < cnt / 2; i += blockDim.x) {
+        const int b = (i / k2) * 2 * step, t = i % k2;
+        const int j = t ^ stride;
+        if (b < cnt && j > t) {
+          const TopItem a = s[b + t], c = s[b + j];
+          if (before(c, a)) {
+            s[b + t] = c;
+            s[b + j] = a;
           }
         }
       }
@@ -141,7 +174,9 @@ topk_round_kernel(const double* __restrict__ tau, const TopItem* __restrict__ in
     s_items[i] = t;
   }
   __syncthreads();
-  bitonic_items(s_items, cnt);
+  int k2 = 1;
+  while (k2 < k) k2 <<= 1;
+  topk_items(s_items, cnt, k2);
   for (int i = threadIdx.x; i < k; i += blockDim.x)
     out[qi * out_len + (int64_t)blockIdx.x * k + i] = s_items[i];
 }
