@@ -13,6 +13,7 @@ struct DbView {
   int scheme = 0;
   int32_t* heavy = nullptr;        // heavy-row list of the database
   int32_t* heavy_count = nullptr;
+  int32_t heavy_rows = -1;         // its length, read back once (-1: unknown)
 };
 
 // One query launch: nq query rows against all m database rows.

@@ -276,7 +276,8 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
   MatDesc qdesc = matdesc(scratch, nq, n, none, db.scheme, 8, 0, 0, status);
   if (clear_words((int32_t*)scratch, 2, s) != KTAU_OK) return KTAU_EDEVICE;
   if (prepass_ws(Q, nq, n, scratch, nullptr, status, s) != KTAU_OK) return KTAU_EDEVICE;
-  if (launch_heavy(qdesc, s) != hipSuccess) return KTAU_EDEVICE;
+  const bool composite = db.heavy_rows != 0 && n <= kCompositeMaxN;
+  if (composite && launch_heavy(qdesc, s) != hipSuccess) return KTAU_EDEVICE;
 
   QueryDesc qd;
   memset(&qd, 0, sizeof(qd));
@@ -300,7 +301,7 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
 #undef KTAU_CASE
     default: e = hipErrorInvalidValue; break;
   }
-  if (e == hipSuccess) e = query_composite(qd, s);
+  if (e == hipSuccess && composite) e = query_composite(qd, s);
   if (e != hipSuccess) return KTAU_EDEVICE;
 
   // top-k rounds: tau -> ia -> ib -> ia ...
@@ -367,6 +368,12 @@ int ktau_db_create(const float* X, int64_t m, int64_t n, void* stream, ktau_db**
   if (rc == KTAU_OK) {
     rc = ktau_status(db->ws, stream);
   }
+  // the number of heavy database rows: without any, no query pair can need
+  // the composite pass and queries skip it
+  if (rc == KTAU_OK &&
+      hipMemcpy(&db->v.heavy_rows, db->v.heavy_count, sizeof(int32_t), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    rc = KTAU_EDEVICE;
   if (rc != KTAU_OK) {
     (void)hipFree(db->ws);
     delete db;
