@@ -175,6 +175,10 @@ def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
             "plans": [f"{s}/q{q}" for s, q in classes]}
 
 
+def scheme_label(K, scheme: int) -> str:
+    return K.NAIVE_SCHEME_NAME if scheme == K.KTAU_SCHEME_NAIVE else K.ktau_scheme_names()[scheme]
+
+
 def plain_timing(K, torch, stream, X, reps: int) -> dict:
     """Mean time of the plain path (pre-pass + pair kernel) on matrix X."""
     Xd = torch.from_numpy(X).cuda()
@@ -200,7 +204,7 @@ def plain_timing(K, torch, stream, X, reps: int) -> dict:
         raise RuntimeError(f"plain call on {m} x {n} failed")
     ms = e0.elapsed_time(e1) / reps
     return {"m": m, "n": n, "pairs": P, "ms": ms, "pairs_per_s": P / (ms * 1e-3),
-            "scheme": K.ktau_scheme_names()[K.ktau_default_scheme(n)],
+            "scheme": scheme_label(K, K.ktau_plain_default_scheme(n)),
             "merge_steps_per_s": P * merge_steps(n) / (ms * 1e-3)}
 
 
@@ -218,6 +222,61 @@ def other_shapes(K, synth, torch, stream, reps: int) -> dict:
     samples["workload"] = ("sample-vs-sample m=353 n=17941: per-gene level + 4 group offsets + "
                            "noise, exp, 2% exact zeros, seed 6")
     return {"gene_vs_gene": genes, "sample_vs_sample": samples}
+
+
+def small_n(K, synth, torch, stream, reps: int) -> dict:
+    """Short rows: the naive count (every sample pair compared, Sec. 2) from
+    per-row bit sets against the default network scheme, pair kernel alone on
+    4096 log-normal rows (blocks of 64 at rho 0.6, 2% exact zeros) per n; and
+    the 64 x 128 rounded-normal case end to end (pre-pass + pairs), which is
+    launch-bound."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = []
+    for n in (32, 64, 128, 256):
+        X = synth.lognormal_blocks(4096, n, 500 + n)
+        m = X.shape[0]
+        P = m * (m - 1) // 2
+        Xd = torch.from_numpy(X).cuda()
+        ws = K.alloc_workspace(m, n, Xd.device)
+        out = K.alloc_outputs(P, m, Xd.device)
+        K.ktau_prepare(Xd, ws, out["n1"], stream=stream)
+        net = K.ktau_default_scheme(n)
+        row = {"n": n, "m": m, "pairs": P, "network_scheme": K.ktau_scheme_names()[net]}
+        for name, scheme in (("naive_bits", K.NAIVE_SCHEME_NAME), ("network", net)):
+            ms = timed(lambda: K.ktau_pairs(m, n, out, ws, scheme=scheme, stream=stream))
+            row[f"{name}_ms"] = ms
+            row[f"{name}_pairs_per_s"] = P / (ms * 1e-3)
+        if K.ktau_status(ws) != K.KTAU_OK:
+            raise RuntimeError(f"short-row timing on {m} x {n} failed")
+        row["naive_speedup"] = row["network_ms"] / row["naive_bits_ms"]
+        rows.append(row)
+    X = synth.config_matrix(1)
+    m, n = X.shape
+    P = m * (m - 1) // 2
+    Xd = torch.from_numpy(X).cuda()
+    ws = K.alloc_workspace(m, n, Xd.device)
+    out = K.alloc_outputs(P, m, Xd.device)
+    c1 = {"m": m, "n": n, "pairs": P}
+    for name, scheme in (("naive_bits", K.NAIVE_SCHEME_NAME),
+                         ("network", K.ktau_default_scheme(n))):
+        c1[f"{name}_us"] = 1e3 * timed(
+            lambda: K.ktau_allpairs_ex(Xd, -1, -1, out, ws, scheme, 0, stream))
+    if K.ktau_status(ws) != K.KTAU_OK:
+        raise RuntimeError("64 x 128 timing failed")
+    return {"workload": "m=4096 log-normal blocks (seed 500+n), pair kernel alone; "
+                        "64x128 rounded normals (seed 1) end to end",
+            "rows": rows, "c1_64x128": c1}
 
 
 def perm_test(K, synth, torch, stream, reps: int) -> dict:
@@ -374,6 +433,8 @@ def main() -> int:
     ap.add_argument("--no-shapes", action="store_true",
                     help="skip the gene-vs-gene and sample-vs-sample shapes")
     ap.add_argument("--no-perm", action="store_true", help="skip the permutation test")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the short-row (naive count vs network) timing")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="target length of each Poisson run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -526,6 +587,8 @@ def main() -> int:
         result["shapes"] = other_shapes(K, synth, torch, stream, max(2, args.steps))
     if not args.no_perm:
         result["perm_test"] = perm_test(K, synth, torch, stream, 2)
+    if not args.no_small:
+        result["small_n"] = small_n(K, synth, torch, stream, 5)
     if not args.no_serve:
         result["serving"] = serving(K, synth, torch, stream, args.serve_seconds)
         rates = result["serving"]["at_rates"]

@@ -121,7 +121,9 @@ typedef struct ktau_pair_out {
   int64_t* n1;     /* per-row tie term; n2 of (y, x) = n1[x] [m]  */
 } ktau_pair_out;
 
-/* Bytes of device workspace the all-pairs calls need for (m, n). */
+/* Bytes of device workspace the all-pairs calls need for (m, n) (for
+ * n <= 256 this includes the bit sets of KTAU_SCHEME_NAIVE,
+ * 8 n ceil(n/32) bytes per row, rounded up to 1, 2, 4 or 8 words per set). */
 size_t ktau_allpairs_workspace_size(int64_t m, int64_t n);
 
 /* All m(m-1)/2 strict pairs of X_dev (m x n float32, row-major).  The
@@ -141,11 +143,12 @@ int ktau_allpairs_range(const float* X_dev, int64_t m, int64_t n,
 /* The two halves of ktau_allpairs, for callers that rank once and then make
  * several passes over job sub-ranges (Sec. 4.3) or time the halves apart.
  * ktau_prepare clears the workspace status and runs the rank pre-pass of X
- * into the workspace (writing out_n1_dev[m] too if it is not NULL).
+ * into the workspace (writing out_n1_dev[m] too if it is not NULL), and for
+ * n <= 256 the bit sets of KTAU_SCHEME_NAIVE.
  * ktau_pairs computes jobs [J_begin, J_end) (J_begin < 0: all jobs, in tile
  * order) from a workspace prepared for the same (m, n); scheme < 0 and q <= 0
- * pick the defaults (ktau_default_scheme(n); tile edge 8 for n <= 4096, 4 for
- * n <= 16384, else 2). */
+ * pick the defaults (ktau_plain_default_scheme(n); tile edge 16 for
+ * KTAU_SCHEME_NAIVE, else 8 for n <= 4096, 4 for n <= 16384, 2 beyond). */
 int ktau_prepare(const float* X_dev, int64_t m, int64_t n, int64_t* out_n1_dev,
                  void* workspace_dev, size_t ws_bytes, void* stream);
 int ktau_pairs(int64_t m, int64_t n, int64_t J_begin, int64_t J_end,
@@ -166,14 +169,29 @@ int ktau_status(void* workspace_dev, void* stream);
  * n <= lanes * K.
  * ------------------------------------------------------------------------- */
 
+/* The naive count of Sec. 2 (Algorithm 1: all n(n-1)/2 sample pairs of a
+ * pair of rows compared), as a scheme of the plain entry points only
+ * (ktau_pairs, ktau_allpairs_ex) for n <= 256.  The comparisons are made once
+ * per row by ktau_prepare and kept in the workspace as bit sets (for every
+ * sample, the samples ranked below it and those tied with it), so a pair
+ * costs an AND and a population count per 32 sample pairs; counts and tau are
+ * the same, bit for bit, as the network schemes'.  Its default tile edge is
+ * 16.  Not a member of the numbered schemes (ktau_scheme_count); the batched,
+ * query and permutation-test calls do not take it. */
+#define KTAU_SCHEME_NAIVE 100
+
 int ktau_scheme_count(void);
 const char* ktau_scheme_name(int scheme);      /* "invalid" if out of range   */
 int64_t ktau_scheme_capacity(int scheme);      /* largest n; -1 if invalid    */
 int ktau_default_scheme(int64_t n);
+/* The scheme the plain calls pick for n: KTAU_SCHEME_NAIVE where it measured
+ * faster than the network, else ktau_default_scheme(n). */
+int ktau_plain_default_scheme(int64_t n);
 
 /* ktau_allpairs (J_begin < 0) or ktau_allpairs_range (J_begin >= 0) with the
- * scheme and tile edge q (1..64) chosen by the caller; scheme < 0 or q <= 0
- * pick the defaults.  KTAU_EINVAL if the scheme cannot hold n. */
+ * scheme (a numbered scheme or KTAU_SCHEME_NAIVE) and tile edge q (1..64)
+ * chosen by the caller; scheme < 0 or q <= 0 pick the defaults.  KTAU_EINVAL
+ * if the scheme cannot hold n. */
 int ktau_allpairs_ex(const float* X_dev, int64_t m, int64_t n, int64_t J_begin,
                      int64_t J_end, ktau_pair_out out, void* workspace_dev,
                      size_t ws_bytes, int scheme, int q, void* stream);

@@ -170,6 +170,15 @@ __host__ __device__ inline int64_t direct_budget(int64_t n) {
   return 4 * n * lg;
 }
 
+// Rows of at most kBitsMaxN samples can also be counted by the naive
+// comparison of every sample pair, with each row's comparisons stored once as
+// bit sets (ktau_bits.hip): bits_words_per_set(n) words per set, two sets per
+// sample, bits_bytes(m, n) bytes behind the plain workspace.
+constexpr int64_t kBitsMaxN = 256;
+constexpr int kBitsQ = 16;              // default tile edge of that path
+size_t bits_words_per_set(int64_t n);
+size_t bits_bytes(int64_t m, int64_t n);
+
 // One matrix as seen by the pair kernels.
 struct MatDesc {
   RankView rv;
@@ -216,6 +225,11 @@ hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s);
 hipError_t launch_pairs_persistent(int scheme, const MatDesc* descs_dev, int64_t count,
                                    int64_t total_units, const int64_t* unit_prefix_dev,
                                    int64_t* counters_dev, const int32_t* status, hipStream_t s);
+
+// Bit sets of every row of a prepared matrix (n <= kBitsMaxN), and the naive
+// pair count from them over all tiles or over jobs [J_begin, J_end).
+hipError_t launch_bits_prepass(const MatDesc& d, uint32_t* bits, hipStream_t s);
+hipError_t launch_bits_pairs(const MatDesc& d, const uint32_t* bits, bool tiles, hipStream_t s);
 
 // Heavy-row lists and the composite pass for every matrix of a table.
 hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, int max_n,

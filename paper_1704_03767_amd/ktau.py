@@ -26,6 +26,8 @@ KTAU_ENAN = -6
 KTAU_ECANCELED = -7
 KTAU_ETIMEDOUT = -8
 KTAU_MAX_N = 32768
+KTAU_SCHEME_NAIVE = 100       # naive bit-set count, plain calls, n <= 256
+NAIVE_SCHEME_NAME = "naive_bits"
 
 _lock = threading.Lock()
 _lib = None
@@ -64,6 +66,7 @@ def _declare(lib):
         "ktau_scheme_name": ([i32], ctypes.c_char_p),
         "ktau_scheme_capacity": ([i32], i64),
         "ktau_default_scheme": ([i64], i32),
+        "ktau_plain_default_scheme": ([i64], i32),
         "ktau_perm_workspace_size": ([i64, i64, i64], sz),
         "ktau_probe_threads": ([], i32),
         "ktau_probe_valu_ops_per_iter": ([], i32),
@@ -152,10 +155,16 @@ def ktau_default_scheme(n: int) -> int:
     return int(lib().ktau_default_scheme(int(n)))
 
 
+def ktau_plain_default_scheme(n: int) -> int:
+    return int(lib().ktau_plain_default_scheme(int(n)))
+
+
 def scheme_id(scheme) -> int:
     if scheme is None:
         return -1
     if isinstance(scheme, str):
+        if scheme == NAIVE_SCHEME_NAME:
+            return KTAU_SCHEME_NAIVE
         return ktau_scheme_names().index(scheme)
     return int(scheme)
 

@@ -60,6 +60,11 @@ def test_host_side_argument_errors():
                               None) == K.KTAU_EINVAL
     assert L.ktau_allpairs_ex(fake, 30, 30, -1, -1, _out(), ws, 1 << 30, -1, 65,
                               None) == K.KTAU_EINVAL
+    # the naive bit-set scheme takes rows of at most 256 samples
+    assert L.ktau_allpairs_ex(fake, 30, 257, -1, -1, _out(), ws, 1 << 30, K.KTAU_SCHEME_NAIVE, 0,
+                              None) == K.KTAU_EINVAL
+    assert L.ktau_pairs(30, 257, -1, -1, _out(), ws, 1 << 30, K.KTAU_SCHEME_NAIVE, 0,
+                        None) == K.KTAU_EINVAL
     assert L.ktau_allpairs_workspace_size(1, 10) == 0
     assert L.ktau_allpairs_workspace_size(10, K.KTAU_MAX_N + 1) == 0
     assert L.ktau_rank(None, 3, 3, None, None, None, None, fake, None, 0, None) == K.KTAU_EINVAL
@@ -76,7 +81,8 @@ def test_host_side_argument_errors():
                        None) == K.KTAU_ENOMEM
     # permutation test: host-side argument checks
     need = L.ktau_perm_workspace_size(10, 100, 4)
-    assert need > L.ktau_allpairs_workspace_size(10, 100) and L.ktau_perm_workspace_size(10, 100, 0) == 0
+    assert need > 0 and L.ktau_perm_workspace_size(10, 100, 0) == 0
+    assert L.ktau_perm_workspace_size(10, 300, 4) > L.ktau_allpairs_workspace_size(10, 300)
     assert L.ktau_perm_test(fake, 10, 100, None, 4, -1, -1, fake, None, fake, need,
                             None) == K.KTAU_EINVAL
     assert L.ktau_perm_test(fake, 10, 100, fake, 0, -1, -1, fake, None, fake, need,
@@ -101,6 +107,17 @@ def test_scheme_table():
         s = K.ktau_default_scheme(n)
         assert caps[s] >= n
     assert K.ktau_scheme_capacity(-1) == -1
+
+
+def test_workspace_holds_the_bit_sets():
+    # rows of <= 256 samples: two sets of ceil(n/32) words (rounded to 1, 2, 4
+    # or 8) per sample behind the rank layout
+    for n, words in ((32, 1), (33, 2), (64, 2), (100, 4), (128, 4), (129, 8), (256, 8)):
+        m = 50
+        assert K.ktau_allpairs_workspace_size(m, n) >= 2 * m * n * words * 4 + 3 * m * 128 * 2
+    big = K.ktau_allpairs_workspace_size(50, 257)
+    assert big < K.ktau_allpairs_workspace_size(50, 256)
+    assert K.ktau_plain_default_scheme(1024) == K.ktau_default_scheme(1024)
 
 
 def test_workspace_size_grows_with_shape():
