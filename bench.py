@@ -225,7 +225,7 @@ def other_shapes(K, synth, torch, stream, reps: int) -> dict:
 
 
 def small_n(K, synth, torch, stream, reps: int) -> dict:
-    """Short rows: the naive count (every sample pair compared, Sec. 2) from
+    """Short rows: the naive count (every sample pair compared, Sec. 3.1) from
     per-row bit sets against the default network scheme, pair kernel alone on
     4096 log-normal rows (blocks of 64 at rho 0.6, 2% exact zeros) per n; and
     the 64 x 128 rounded-normal case end to end (pre-pass + pairs), which is

@@ -169,7 +169,7 @@ int ktau_status(void* workspace_dev, void* stream);
  * n <= lanes * K.
  * ------------------------------------------------------------------------- */
 
-/* The naive count of Sec. 2 (Algorithm 1: all n(n-1)/2 sample pairs of a
+/* The naive count of Sec. 3.1 (Algorithm 1: all n(n-1)/2 sample pairs of a
  * pair of rows compared), as a scheme of the plain entry points only
  * (ktau_pairs, ktau_allpairs_ex) for n <= 256.  The comparisons are made once
  * per row by ktau_prepare and kept in the workspace as bit sets (for every

@@ -1,4 +1,4 @@
-// The naive count (Sec. 2, Algorithm 1: every sample pair compared, O(n^2)
+// The naive count (Sec. 3.1, Algorithm 1: every sample pair compared, O(n^2)
 // per pair of rows) for short rows, with the comparisons done once per row
 // and stored as bit sets, so that a pair of rows costs one AND and one
 // population count per 32 sample pairs.
