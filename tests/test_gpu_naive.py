@@ -177,3 +177,27 @@ def test_naive_nan_is_reported():
     assert e.value.status == K.KTAU_ENAN
     _assert_same(_run(synth.config_matrix(1), scheme=NAIVE),
                  oracle.allpairs(synth.config_matrix(1), "gse"))
+
+
+def test_naive_random_shapes_equal_network():
+    # seeded shapes across both kernels (job order below 2^20 pairs, tiles
+    # above) and every set width, with a mix of tie structures per row;
+    # every output compared with a network scheme, 500 pairs with the oracle
+    rng = np.random.default_rng(77)
+    for t in range(12):
+        m = int(rng.integers(2, 2200))
+        n = int(rng.integers(2, 257))
+        X = rng.standard_normal((m, n)).astype(np.float32)
+        kind = rng.integers(0, 4, m)
+        X[kind == 1] = np.round(X[kind == 1], 1)
+        X[kind == 2] = rng.integers(0, 3, (int((kind == 2).sum()), n)).astype(np.float32)
+        X[kind == 3] = np.where(rng.random((int((kind == 3).sum()), n)) < 0.1, 0.0,
+                                X[kind == 3]).astype(np.float32)
+        a = _run(X, scheme=NAIVE)
+        b = _run(X, scheme=K.ktau_default_scheme(n))
+        for k in ("nc", "nd", "n3", "tau_b", "tau_a", "n1"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), (t, m, n, k)
+        P = m * (m - 1) // 2
+        J = np.unique(rng.integers(0, P, min(P, 500)))
+        yx = np.array([K.ktau_job_to_pair(m, int(j)) for j in J])
+        _assert_same(a, oracle.pairs(X, yx[:, 0], yx[:, 1], "gse"), slots=J)
