@@ -13,8 +13,11 @@
 //   n3  = (sum_a |EQ_u[a] & EQ_v[a]| - n) / 2   (both rows tied; b = a drops out)
 // and n_c, tau_B, tau_A follow from n0, n1, n2 as on the other paths.  The
 // counts are those of the definition (Eq. 1-3), so they equal the network's
-// bit for bit.  Rows of at most 256 samples only: the sets take n ceil(n/32)
-// words per row, and the count grows as n^2/32.
+// bit for bit.  Only samples tied with another sample of u can add to n3, so
+// only their lanes read EQ sets.  Rows of at most 256 samples only: the two
+// sets take 2 n w words per row (w = ceil(n/32) rounded up to 1, 2, 4 or 8),
+// and the count grows as n^2/32.  Matrices of up to 2^20 pairs run one group
+// per pair in job order; larger ones run q x q tiles.
 #include "ktau_order.h"
 #include "ktau_pairdev.h"
 
