@@ -118,6 +118,13 @@ def test_workspace_holds_the_bit_sets():
     big = K.ktau_allpairs_workspace_size(50, 257)
     assert big < K.ktau_allpairs_workspace_size(50, 256)
     assert K.ktau_plain_default_scheme(1024) == K.ktau_default_scheme(1024)
+    # the plain calls take the naive bit-set count up to n = 128 (where it
+    # measured faster), the network beyond
+    for n in (2, 32, 64, 100, 128):
+        assert K.ktau_plain_default_scheme(n) == K.KTAU_SCHEME_NAIVE
+    for n in (129, 256, 4096):
+        assert K.ktau_plain_default_scheme(n) == K.ktau_default_scheme(n)
+    assert K.scheme_id(K.NAIVE_SCHEME_NAME) == K.KTAU_SCHEME_NAIVE
 
 
 def test_workspace_size_grows_with_shape():
