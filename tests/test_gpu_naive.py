@@ -201,3 +201,20 @@ def test_naive_random_shapes_equal_network():
         J = np.unique(rng.integers(0, P, min(P, 500)))
         yx = np.array([K.ktau_job_to_pair(m, int(j)) for j in J])
         _assert_same(a, oracle.pairs(X, yx[:, 0], yx[:, 1], "gse"), slots=J)
+
+
+@pytest.mark.parametrize("scheme", [NAIVE, "network"])
+def test_tau_a_only_outputs(scheme):
+    # tau_A alone (every other output NULL), as the naive kernel of the paper
+    # computes it; the kernels skip the NULL arrays
+    X = synth.gaussian_rounded(200, 128, 31)
+    m, n = X.shape
+    P = m * (m - 1) // 2
+    Xd = torch.from_numpy(X).cuda()
+    out = {"tau_a": torch.full((P,), -7.0, dtype=torch.float64, device=Xd.device)}
+    ws = K.alloc_workspace(m, n, Xd.device)
+    s = NAIVE if scheme == NAIVE else K.ktau_default_scheme(n)
+    K.ktau_allpairs_ex(Xd, -1, -1, out, ws, s, 0)
+    assert K.ktau_status(ws) == K.KTAU_OK
+    want = oracle.allpairs(X, "gse")
+    _assert_tau(out["tau_a"].cpu().numpy(), want["tau_a"], "tau_a")
