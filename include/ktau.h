@@ -19,7 +19,10 @@
  * per-row rank pre-pass done once per row, Sec. 3), v permuted into that order,
  * discordant pairs counted as strict inversions (Step 3; Algorithm 2 counts
  * them by merge sort, the kernels here by a bitonic network that yields the
- * same count), tie runs scanned.  Pairs are numbered by the job-id bijection of Sec. 4.1
+ * same count), tie runs scanned.  The plain calls count rows of up to 128
+ * samples by default with the naive comparison of every sample pair instead
+ * (Sec. 3.1), done as per-row bit sets (KTAU_SCHEME_NAIVE below), which gives
+ * the same counts.  Pairs are numbered by the job-id bijection of Sec. 4.1
  * (Eq. 4-10) restricted to the strict upper triangle: row-major, y < x,
  *     J(y, x) = F(y) + (x - y - 1),  F(y) = y (2(m-1) - y + 1) / 2,
  * J in [0, m(m-1)/2).  Work is spread in q x q tiles numbered by Eq. 11-14.
