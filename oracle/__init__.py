@@ -8,8 +8,8 @@ C, compiled here with gcc), and this module only marshals numpy arrays.
 Two pair routines, both from the paper:
   * ``"brute"`` -- the definition of concordant / discordant / tied pairs
     (Sec. 1, and the naive kernel of Sec. 3.1 generalised to all five counts);
-  * ``"gse"``   -- the sorting-enabled kernel, Steps 1-5 of Sec. 3.2 with the
-    merge of Algorithm 2.
+  * ``"gse"``   -- the sorting-enabled kernel, Steps 1-5 of Sec. 3.2, with
+    Step 3's discordant count taken by a top-down merge count.
 tau_B (Eq. 3) and tau_A (Eq. 1) follow from the integer counts.
 
 Also a permutation test of tau (Sec. 1 names it for P-values): the samples of

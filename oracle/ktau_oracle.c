@@ -15,15 +15,15 @@
  *                        tau_A to all five counts): every sample pair a<b is
  *                        classified by float comparisons.  O(n^2).
  *   B  ko_pair_gse    -- the paper's sorting-enabled kernel (Sec. 3.2, Steps
- *                        1-5, Step 3 as in Algorithm 2): sort the joint pairs
- *                        by (u, v), scan for n1 and n3, bottom-up merge sort
- *                        on v counting strictly smaller right elements, scan
- *                        for n2, numerator from the tie counts.  O(n log n).
+ *                        1-5): sort the joint pairs by (u, v), scan for n1
+ *                        and n3, count the strictly decreasing pairs of v in
+ *                        that order (Step 3, by a top-down merge count written
+ *                        from that definition), scan for n2, numerator from
+ *                        the tie counts.  O(n log n).
  * Readings of the paper taken here (each also listed in the design notes):
  *   - ties are IEEE float32 equality, so -0.0 ties with +0.0; NaN is refused;
- *   - the Algorithm 2 merge also copies whichever run is left over (its
- *     listing stops at the first exhausted run; later widths need the data);
- *   - the Step 3 remark about the "left" subarray is read as the right one;
+ *   - Step 3 counts a pair only when v strictly decreases (equal v is a tie,
+ *     not a discordant pair), whatever merge schedule reaches the count;
  *   - tau_B = (double)(nc-nd) / sqrt((double)(n0-n1) * (double)(n0-n2)),
  *     IEEE round-to-nearest, no fused multiply-add; 0/0 gives NaN;
  *   - the all-pairs output is the strict upper triangle (y < x), numbered
@@ -89,42 +89,32 @@ static int ko_joint_cmp(const void* pa, const void* pb) {
   return ko_cmp(a->v, b->v);
 }
 
-/* One out-of-place merge of in[left, mid) and in[mid, right) by v.  A right
- * element strictly smaller than the current left element is discordant with
- * every left element not yet taken (mid - l of them).  Both leftover runs are
- * copied so the next width sees all data. */
-static int64_t ko_gse_merge(const ko_joint* in, ko_joint* out, int64_t left,
-                            int64_t mid, int64_t right) {
-  int64_t l = left, r = mid, p = left, nd = 0;
-  while (l < mid && r < right) {
-    if (in[r].v < in[l].v) {
-      nd += mid - l;
-      out[p++] = in[r++];
-    } else {
-      out[p++] = in[l++];
-    }
+/* Step 3: n_d is the number of index pairs i < j of the (u, v)-ordered
+ * sequence whose v values are strictly decreasing, v_i > v_j (Sec. 3.2; the
+ * count does not depend on which merge tree reaches it).  Counted top-down:
+ * split the index range into a lower and an upper half, count inside each
+ * half (which leaves each half ordered by v), then add the pairs with i in the
+ * lower and j in the upper half: for every upper element, in ascending v, the
+ * lower elements with a strictly larger v -- all lower elements except those
+ * with v at or below it, which a single pointer over the ordered lower half
+ * counts.  The two halves are then merged by v (lower first on equal v) so the
+ * caller sees its range ordered by v.  tmp holds n entries. */
+static int64_t ko_inversions(ko_joint* a, ko_joint* tmp, int64_t n) {
+  if (n < 2) return 0;
+  const int64_t h = n / 2;
+  int64_t count = ko_inversions(a, tmp, h) + ko_inversions(a + h, tmp, n - h);
+  int64_t at_or_below = 0;
+  for (int64_t j = h; j < n; ++j) {
+    while (at_or_below < h && a[at_or_below].v <= a[j].v) ++at_or_below;
+    count += h - at_or_below;
   }
-  while (l < mid) out[p++] = in[l++];
-  while (r < right) out[p++] = in[r++];
-  return nd;
-}
-
-/* Step 3: bottom-up merge sort by v with widths 1, 2, 4, ...  Returns n_d;
- * on return pairs[] is sorted by v. */
-static int64_t ko_gse_step3(ko_joint* pairs, ko_joint* buffer, int64_t n) {
-  int64_t nd = 0;
-  ko_joint* in = pairs;
-  ko_joint* out = buffer;
-  for (int64_t s = 1; s < n; s *= 2) {
-    for (int64_t l = 0; l < n; l += 2 * s) {
-      int64_t mid = l + s < n ? l + s : n;
-      int64_t r = l + 2 * s < n ? l + 2 * s : n;
-      nd += ko_gse_merge(in, out, l, mid, r);
-    }
-    ko_joint* t = in; in = out; out = t;
+  int64_t i = 0, j = h, p = 0;
+  while (i < h || j < n) {
+    if (j == n || (i < h && a[i].v <= a[j].v)) tmp[p++] = a[i++];
+    else tmp[p++] = a[j++];
   }
-  if (in != pairs) memcpy(pairs, in, (size_t)n * sizeof(ko_joint));
-  return nd;
+  memcpy(a, tmp, (size_t)n * sizeof(ko_joint));
+  return count;
 }
 
 /* Number of tied pairs sum t(t-1)/2 over runs of equal keys in a sorted list;
@@ -160,7 +150,7 @@ static void ko_pair_gse_work(const float* u, const float* v, int64_t n,
   qsort(pairs, (size_t)n, sizeof(ko_joint), ko_joint_cmp);   /* Step 1 */
   int64_t n1 = ko_run_pairs(pairs, n, 0);                    /* Step 2 */
   int64_t n3 = ko_run_pairs(pairs, n, 2);
-  int64_t nd = ko_gse_step3(pairs, buffer, n);               /* Step 3 */
+  int64_t nd = ko_inversions(pairs, buffer, n);              /* Step 3 */
   int64_t n2 = ko_run_pairs(pairs, n, 1);                    /* Step 4 */
   int64_t n0 = n * (n - 1) / 2;                              /* Step 5 */
   c->nd = nd;
