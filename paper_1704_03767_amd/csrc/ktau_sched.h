@@ -11,7 +11,9 @@
 //     pool (first fit); otherwise it waits until running launches free
 //     memory -- so requests that arrive while others run are admitted as
 //     slots and memory free up, and their work overlaps on the device;
-//   * a request flagged for a forced failure always runs alone.
+//   * a request flagged for a forced failure always runs alone;
+//   * a launch whose start fails part-way is drained (the executor waits for
+//     what it already enqueued) before its memory returns to the pool.
 #pragma once
 
 #include <stdint.h>
@@ -105,6 +107,9 @@ class Executor {
   virtual size_t bytes_for(int64_t nq, int64_t k) const = 0;
   // enqueue the launch's work; non-zero = it could not be started
   virtual int start(Launch& l) = 0;
+  // after start() failed: returns only once nothing that start() may already
+  // have enqueued can still touch the launch's pool region or staging
+  virtual void abandon(Launch& l) = 0;
   // has the launch finished (results ready to collect)?
   virtual bool finished(const Launch& l) = 0;
   // copy results into the requests; returns the launch status
@@ -214,7 +219,12 @@ class Scheduler {
       stats_.launches++;
       stats_.merged += (int64_t)take - 1;
       const int st = l->fail ? 0 : ex_->start(*l);
-      if (st != 0) l->fail = true;   // collected as a failure on the next pass
+      if (st != 0) {
+        // work already enqueued may still write the region: drain it before
+        // the failure is collected and the region goes back to the pool
+        ex_->abandon(*l);
+        l->fail = true;   // collected as a failure on the next pass
+      }
       ++running_;
       if (running_ > stats_.peak_running) stats_.peak_running = running_;
       if (pool_.used() > stats_.peak_bytes) stats_.peak_bytes = pool_.used();

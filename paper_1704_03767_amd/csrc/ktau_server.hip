@@ -108,6 +108,8 @@ class GpuExecutor : public sched::Executor {
     return KTAU_OK;
   }
 
+  void abandon(Launch& l) override { (void)hipStreamSynchronize(slots_[l.slot].stream); }
+
   bool finished(const Launch& l) override {
     return hipEventQuery(slots_[l.slot].done) != hipErrorNotReady;
   }

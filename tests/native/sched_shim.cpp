@@ -12,10 +12,30 @@ namespace {
 struct Fake : Executor {
   size_t per_query = 1000;
   std::vector<bool> done;          // per slot
+  // regions with work still "in flight" (enqueued by a start that failed,
+  // not yet drained), and tickets whose start fails after enqueueing
+  std::vector<std::pair<size_t, size_t>> inflight;
+  std::vector<int64_t> fail_start;
+  int overlaps = 0, abandoned = 0;
   size_t bytes_for(int64_t nq, int64_t) const override { return (size_t)nq * per_query; }
   int start(Launch& l) override {
     done[l.slot] = false;
+    for (auto& r : inflight)
+      if (l.off < r.first + r.second && r.first < l.off + l.bytes) ++overlaps;
+    for (int64_t t : fail_start)
+      if (!l.reqs.empty() && l.reqs[0]->ticket == t) {
+        inflight.push_back({l.off, l.bytes});   // work enqueued, then an error
+        return -4;
+      }
     return 0;
+  }
+  void abandon(Launch& l) override {
+    ++abandoned;
+    for (auto it = inflight.begin(); it != inflight.end(); ++it)
+      if (it->first == l.off) {
+        inflight.erase(it);
+        break;
+      }
   }
   bool finished(const Launch& l) override { return done[l.slot]; }
   int collect(Launch& l) override {
@@ -64,6 +84,10 @@ long long st_submit(void* p, long long nq, long long k, int force_fail) {
 int st_step(void* p) { return (int)((World*)p)->s->step().size(); }
 
 void st_finish_slot(void* p, int slot) { ((World*)p)->ex.done[slot] = true; }
+void st_fail_start(void* p, long long t) { ((World*)p)->ex.fail_start.push_back(t); }
+int st_overlaps(void* p) { return ((World*)p)->ex.overlaps; }
+int st_abandoned(void* p) { return ((World*)p)->ex.abandoned; }
+int st_inflight(void* p) { return (int)((World*)p)->ex.inflight.size(); }
 
 int st_state(void* p, long long t) { return ((World*)p)->reqs[t]->state; }
 int st_status(void* p, long long t) { return ((World*)p)->reqs[t]->status; }

@@ -29,7 +29,8 @@ def lib(tmp_path_factory):
         ("st_batch_queries", [p, ll], ll), ("st_result0", [p, ll], ll),
         ("st_pool_used", [p], ll), ("st_running", [p], ll), ("st_queued", [p], ll),
         ("st_cancel", [p, ll], i), ("st_peak_running", [p], ll), ("st_destroy", [p], None),
-        ("st_pool_fuzz", [ll, i, ctypes.c_uint], i),
+        ("st_pool_fuzz", [ll, i, ctypes.c_uint], i), ("st_fail_start", [p, ll], None),
+        ("st_overlaps", [p], i), ("st_abandoned", [p], i), ("st_inflight", [p], i),
     ]:
         f = getattr(L, name)
         f.argtypes = args
@@ -136,3 +137,24 @@ def test_cancel_only_while_queued(lib):
 def test_pool_first_fit(lib):
     for seed in range(5):
         assert lib.st_pool_fuzz(1 << 20, 2000, seed) == 1
+
+
+def test_failed_start_is_drained_before_its_region_is_reused(lib):
+    # a launch whose start enqueues work and then fails must be drained by the
+    # executor before its pool region is handed to another launch
+    w = lib.st_create(2, 64, 4_096, 1000)
+    a = lib.st_submit(w, 4, 5, 0)           # 4000 B: the whole pool (4096)
+    lib.st_fail_start(w, a)
+    b = lib.st_submit(w, 4, 7, 0)           # needs the same region
+    lib.st_step(w)                          # a starts, fails, is drained
+    assert lib.st_abandoned(w) == 1 and lib.st_inflight(w) == 0
+    assert lib.st_state(w, b) == QUEUED
+    lib.st_step(w)                          # a collected as failed; b admitted
+    assert lib.st_status(w, a) == -7 and lib.st_state(w, a) == DONE
+    assert lib.st_state(w, b) == RUNNING
+    assert lib.st_overlaps(w) == 0
+    lib.st_finish_slot(w, 0)
+    lib.st_finish_slot(w, 1)
+    lib.st_step(w)
+    assert lib.st_status(w, b) == 0 and lib.st_pool_used(w) == 0
+    lib.st_destroy(w)
