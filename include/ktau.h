@@ -19,7 +19,8 @@
  * per-row rank pre-pass done once per row, Sec. 3), v permuted into that order,
  * discordant pairs counted as strict inversions (Step 3; Algorithm 2 counts
  * them by merge sort, the kernels here by a bitonic network that yields the
- * same count), tie runs scanned.  The plain calls count rows of up to 128
+ * same count, and for rows of more than 4096 samples by networks on chunks
+ * with merge levels above them), tie runs scanned.  The plain calls count rows of up to 128
  * samples by default with the naive comparison of every sample pair instead
  * (Sec. 3.1), done as per-row bit sets (KTAU_SCHEME_NAIVE below), which gives
  * the same counts.  Pairs are numbered by the job-id bijection of Sec. 4.1
@@ -38,7 +39,8 @@
  *     Host-detectable errors are returned before anything is enqueued; NaN in
  *     the input is found on the device, latched in the workspace header and
  *     reported by ktau_status().  No C++ exception crosses this interface.
- *   - Sizes: 2 <= n <= KTAU_MAX_N, m >= 2 (m < 2^31).
+ *   - Sizes: 2 <= n <= KTAU_MAX_N (KTAU_MAX_N_NETWORK for the query and
+ *     permutation-test calls), m >= 2 (m < 2^31).
  */
 #ifndef KTAU_H
 #define KTAU_H
@@ -60,10 +62,18 @@ extern "C" {
 #define KTAU_ECANCELED -7 /* server: request cancelled or failed in its slot    */
 #define KTAU_ETIMEDOUT -8 /* server: wait timed out                             */
 
-/* Largest sample count n.  Ranks are 16-bit and the pair kernels key every
- * sample by twice its rank in 16 bits (the spare bit carries the sort
- * network's tag), which bounds n by 2^15. */
-#define KTAU_MAX_N 32768
+/* Largest sample count n of the all-pairs, rank and batch calls.  Ranks and
+ * sample indices are 16-bit.  Up to KTAU_MAX_N_NETWORK samples the pair
+ * kernels key every sample by twice its rank in 16 bits (the spare bit carries
+ * the sort network's tag); longer rows, whose ranks need all 16 bits, are
+ * counted twice on two clamped 15-bit halves of the rank range with an exact
+ * correction for the pairs that straddle them (the paper packs ranks into
+ * 16-bit halves for n <= 32767 and names wider keys as the remedy for longer
+ * vectors, Sec. 3.3). */
+#define KTAU_MAX_N 65536
+/* Largest n of the calls that only have the 16-bit network kernels: the
+ * query search and the permutation test (KTAU_ERANGE above it). */
+#define KTAU_MAX_N_NETWORK 32768
 
 /* Human-readable name of a status code (static storage). */
 const char* ktau_status_string(int status);
@@ -124,21 +134,32 @@ typedef struct ktau_pair_out {
   int64_t* n1;     /* per-row tie term; n2 of (y, x) = n1[x] [m]  */
 } ktau_pair_out;
 
-/* Bytes of device workspace the all-pairs calls need for (m, n) (for
- * n <= 256 this includes the bit sets of KTAU_SCHEME_NAIVE,
- * 8 n ceil(n/32) bytes per row, rounded up to 1, 2, 4 or 8 words per set). */
+/* Bytes of device workspace the all-pairs calls need for (m, n): the rank
+ * pre-pass of every row (Sec. 3: each vector ranked once beforehand), about
+ * 10 m ceil128(n) bytes; for n <= 256 also the bit sets of
+ * KTAU_SCHEME_NAIVE, 8 n ceil(n/32) bytes per row rounded up to 1, 2, 4 or 8
+ * words per set; for n > 16384 a sort scratch of up to 256 rows.  0 for an
+ * invalid shape. */
 size_t ktau_allpairs_workspace_size(int64_t m, int64_t n);
 
-/* All m(m-1)/2 strict pairs of X_dev (m x n float32, row-major).  The
- * workspace (>= ktau_allpairs_workspace_size bytes, 256-byte aligned, owned by
- * the caller) receives the rank pre-pass and the status word; it may be
- * reused across calls once the previous call on it has completed. */
+/* All m(m-1)/2 strict pairs of X_dev (m x n float32, row-major): the
+ * all-pairs correlation matrix of Sec. 1 (Eq. 1-3 for every pair of rows),
+ * counted by the sorting method of Sec. 3.2 and numbered by the strict job
+ * bijection (Sec. 4.1).  out's arrays (device, caller-owned, NULL to skip)
+ * receive one entry per job id.  The workspace (>= ktau_allpairs_workspace_size
+ * bytes, 256-byte aligned, owned by the caller) receives the rank pre-pass and
+ * the status word; it may be reused once the previous call on it has
+ * completed.  Errors: KTAU_EINVAL (null X, bad shape, misaligned workspace),
+ * KTAU_ERANGE (n > KTAU_MAX_N), KTAU_ENOMEM (workspace too small),
+ * KTAU_EDEVICE (a launch failed); a NaN is latched for ktau_status. */
 int ktau_allpairs(const float* X_dev, int64_t m, int64_t n, ktau_pair_out out,
                   void* workspace_dev, size_t ws_bytes, void* stream);
 
-/* Jobs J in [J_begin, J_end) only (Sec. 4.3 multi-pass sub-ranges); result
- * slot of job J is J - J_begin.  Any prefix of the job range can be resumed
- * from its end. */
+/* Jobs J in [J_begin, J_end) only: the correlation matrix computed in
+ * job-id sub-ranges over several passes (Sec. 4.3, offload in passes); the
+ * result slot of job J is J - J_begin.  Any prefix of the job range can be
+ * resumed from its end.  Errors as ktau_allpairs, plus KTAU_ERANGE if
+ * 0 <= J_begin <= J_end <= m(m-1)/2 does not hold. */
 int ktau_allpairs_range(const float* X_dev, int64_t m, int64_t n,
                         int64_t J_begin, int64_t J_end, ktau_pair_out out,
                         void* workspace_dev, size_t ws_bytes, void* stream);
@@ -146,12 +167,16 @@ int ktau_allpairs_range(const float* X_dev, int64_t m, int64_t n,
 /* The two halves of ktau_allpairs, for callers that rank once and then make
  * several passes over job sub-ranges (Sec. 4.3) or time the halves apart.
  * ktau_prepare clears the workspace status and runs the rank pre-pass of X
- * into the workspace (writing out_n1_dev[m] too if it is not NULL), and for
- * n <= 256 the bit sets of KTAU_SCHEME_NAIVE.
+ * into the workspace (Sec. 3: ranks, order, tie runs and n1 of every row,
+ * once; writing out_n1_dev[m] too if it is not NULL), and for n <= 256 the
+ * bit sets of KTAU_SCHEME_NAIVE.
  * ktau_pairs computes jobs [J_begin, J_end) (J_begin < 0: all jobs, in tile
- * order) from a workspace prepared for the same (m, n); scheme < 0 and q <= 0
- * pick the defaults (ktau_plain_default_scheme(n); tile edge 16 for
- * KTAU_SCHEME_NAIVE, else 8 for n <= 4096, 4 for n <= 16384, 2 beyond). */
+ * order) from a workspace prepared for the same (m, n): Sec. 3.2 Steps 1-5
+ * per pair with the per-row halves taken from the workspace; scheme < 0 and
+ * q <= 0 pick the defaults (ktau_plain_default_scheme(n); tile edge 16 for
+ * KTAU_SCHEME_NAIVE, else 8 for n <= 4096, 4 for n <= 16384, 2 beyond; the
+ * merge schemes take pairs in job order and ignore q).  Errors as
+ * ktau_allpairs_range, plus KTAU_EINVAL for a scheme that cannot hold n. */
 int ktau_prepare(const float* X_dev, int64_t m, int64_t n, int64_t* out_n1_dev,
                  void* workspace_dev, size_t ws_bytes, void* stream);
 int ktau_pairs(int64_t m, int64_t n, int64_t J_begin, int64_t J_end,
@@ -159,17 +184,25 @@ int ktau_pairs(int64_t m, int64_t n, int64_t J_begin, int64_t J_end,
                int scheme, int q, void* stream);
 
 /* Waits for `stream`, then returns the status latched in a workspace by the
- * last call that used it (KTAU_ENAN if the input held a NaN, KTAU_EINVAL if a
- * permutation given to ktau_perm_test was not one, else KTAU_OK), and clears
- * it. */
+ * last call that used it (KTAU_ENAN if the input held a NaN: a NaN has no
+ * order, so the ranks of Sec. 3 do not exist; KTAU_EINVAL if a permutation
+ * given to ktau_perm_test was not one; else KTAU_OK), and clears it.
+ * KTAU_EDEVICE if the synchronisation or the copy fails. */
 int ktau_status(void* workspace_dev, void* stream);
 
 
 /* ---------------------------------------------------------------------------
  * Per-pair schemes and an explicit-scheme entry point (for tuning and tests).
- * A scheme is a group size (8, 16 or 32 lanes of a wave, a whole 64-lane
- * wave, or a 256-lane workgroup) and a number K of keys per lane; it handles
- * n <= lanes * K.
+ * Network schemes (numbers 0 .. 19) are a group size (8, 16 or 32 lanes of a
+ * wave, a whole 64-lane wave, or a 256-lane workgroup) and a number K of keys
+ * per lane; they sort and count a whole pair in registers and handle
+ * n <= lanes * K (at most 32768).  The merge schemes "merge_k32" and
+ * "merge_k64" (the two numbers after them) give each pair a workgroup of
+ * ceil(n / 64K) waves: each wave sorts and counts a chunk of 64 K samples
+ * with the network, and the merge levels above the chunks are counted by a
+ * merge path in LDS (Algorithm 2's count of right elements taken before
+ * waiting left ones); they handle n <= 32768 and n <= 65536 and are the
+ * default above 4096 samples.
  * ------------------------------------------------------------------------- */
 
 /* The naive count of Sec. 3.1 (Algorithm 1: all n(n-1)/2 sample pairs of a
@@ -192,9 +225,9 @@ int ktau_default_scheme(int64_t n);
 int ktau_plain_default_scheme(int64_t n);
 
 /* ktau_allpairs (J_begin < 0) or ktau_allpairs_range (J_begin >= 0) with the
- * scheme (a numbered scheme or KTAU_SCHEME_NAIVE) and tile edge q (1..64)
- * chosen by the caller; scheme < 0 or q <= 0 pick the defaults.  KTAU_EINVAL
- * if the scheme cannot hold n. */
+ * scheme (a numbered scheme or KTAU_SCHEME_NAIVE) and tile edge q (1..64,
+ * the q x q tiles of Sec. 4.2) chosen by the caller; scheme < 0 or q <= 0 pick
+ * the defaults.  KTAU_EINVAL if the scheme cannot hold n. */
 int ktau_allpairs_ex(const float* X_dev, int64_t m, int64_t n, int64_t J_begin,
                      int64_t J_end, ktau_pair_out out, void* workspace_dev,
                      size_t ws_bytes, int scheme, int q, void* stream);
@@ -300,10 +333,18 @@ int ktau_perm_test(const float* X_dev, int64_t m, int64_t n, const uint16_t* per
 typedef struct ktau_db ktau_db;   /* opaque: ranked database resident in HBM */
 
 /* Ranks the m x n database X_dev once into library-owned device memory
- * (about 10 m ceil128(n) bytes); X_dev may be freed afterwards.  Synchronises
- * `stream`; KTAU_ENAN if X_dev holds a NaN. */
+ * (about 10 m ceil128(n) bytes; Sec. 3: each vector ranked once
+ * beforehand); X_dev may be freed afterwards.  Synchronises `stream`;
+ * KTAU_ENAN if X_dev holds a NaN, KTAU_ERANGE if n > KTAU_MAX_N_NETWORK,
+ * KTAU_EINVAL for a null pointer, m < 1 or n < 2, KTAU_ENOMEM if the device
+ * allocation fails. */
 int ktau_db_create(const float* X_dev, int64_t m, int64_t n, void* stream,
                    ktau_db** db_out);
+/* The same with the network scheme of the query pair kernel chosen by the
+ * caller (scheme < 0: the default for n; KTAU_EINVAL if it is not a network
+ * scheme holding n), for tuning and tests. */
+int ktau_db_create_ex(const float* X_dev, int64_t m, int64_t n, int scheme, void* stream,
+                      ktau_db** db_out);
 void ktau_db_destroy(ktau_db* db);
 int64_t ktau_db_rows(const ktau_db* db);
 int64_t ktau_db_samples(const ktau_db* db);
@@ -388,6 +429,13 @@ int ktau_server_cancel(ktau_server* server, int64_t ticket);
 /* Failure drill: a queued request is launched alone and completes with
  * KTAU_ECANCELED without touching the device (KTAU_EBUSY if not queued). */
 int ktau_server_inject_failure(ktau_server* server, int64_t ticket);
+
+/* Stops (paused != 0) or resumes admitting queued requests to the device.
+ * Submission goes on while paused and running launches complete; requests
+ * queued meanwhile are batched by the policy above when admission resumes.
+ * For operators (draining, maintenance) and for tests that need requests
+ * queued together.  ktau_server_destroy resumes admission itself. */
+int ktau_server_pause(ktau_server* server, int paused);
 
 int ktau_server_stats(ktau_server* server, ktau_server_counters* stats_host);
 

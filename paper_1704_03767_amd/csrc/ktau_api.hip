@@ -44,12 +44,6 @@ int check_shape(int64_t m, int64_t n) {
   return KTAU_OK;
 }
 
-int env_int(const char* name, int dflt) {
-  const char* s = getenv(name);
-  if (!s || !*s) return dflt;
-  return atoi(s);
-}
-
 MatDesc matdesc(void* ws, int64_t m, int64_t n, const ktau_pair_out& out, int scheme, int q,
                 int64_t J_begin, int64_t J_end, int32_t* status) {
   const WsLayout L = ws_layout(m, n);
@@ -87,7 +81,7 @@ int prepass_ws(const float* X, int64_t m, int64_t n, void* ws, int64_t* n1_out, 
   if (launch_prepass(X, m, n, (uint16_t*)(base + L.perm), (uint16_t*)(base + L.rank),
                      (uint16_t*)(base + L.rstart), L.ld, (int64_t*)(base + L.n1), n1_out,
                      (int32_t*)(base + L.nruns), (uint64_t*)(base + L.runs),
-                     status ? status : (int32_t*)base, true, (uint64_t*)(base + L.sort),
+                     status ? status : (int32_t*)base, ws_doubled(n), (uint64_t*)(base + L.sort),
                      s) != hipSuccess)
     return KTAU_EDEVICE;
   return KTAU_OK;
@@ -133,13 +127,13 @@ int check_pairs(int64_t m, int64_t n, int64_t& J_begin, int64_t& J_end, int& sch
     J_end = P;
   }
   if (J_begin > J_end || J_end > P) return KTAU_ERANGE;
-  if (scheme < 0) scheme = env_int("KTAU_FORCE_SCHEME", plain_default_scheme(n));
+  if (scheme < 0) scheme = plain_default_scheme(n);
   if (scheme == KTAU_SCHEME_NAIVE) {
     if (n > kBitsMaxN) return KTAU_EINVAL;
   } else if (scheme < 0 || scheme >= kNumSchemes || scheme_capacity(scheme) < n) {
     return KTAU_EINVAL;
   }
-  if (q <= 0) q = env_int("KTAU_TILE_Q", scheme == KTAU_SCHEME_NAIVE ? kBitsQ : (int)default_q(n));
+  if (q <= 0) q = scheme == KTAU_SCHEME_NAIVE ? kBitsQ : (int)default_q(n);
   if (q < 1 || q > 64) return KTAU_EINVAL;
   return KTAU_OK;
 }

@@ -100,8 +100,13 @@ int64_t tune_rows(int64_t n) {
 // than doubling the padding.
 std::vector<int> candidates(int64_t cls) {
   std::vector<int> v;
-  for (int s = 0; s < kNumSchemes; ++s)
+  for (int s = 0; s < kNumNetSchemes; ++s)
     if (scheme_capacity(s) >= cls && scheme_capacity(s) < 2 * cls) v.push_back(s);
+  // the merge schemes pad only the last chunk, so every class past one
+  // wave's network is theirs too
+  if (cls > 4096)
+    for (int s : {(int)kMergeK32, (int)kMergeK64})
+      if (scheme_capacity(s) >= cls) v.push_back(s);
   return v;
 }
 
@@ -140,6 +145,7 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
     for (int scheme : candidates(cls)) {
       const int q0 = default_q(n);
       for (int q : {q0 / 2, q0, 2 * q0}) {
+        if (is_merge(scheme) && q != q0) continue;   // pairs in job order, no tiles
         MatDesc d = matdesc(ws, m, n, out, scheme, q, 0, P, nullptr);
         float best_ms = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
@@ -173,7 +179,7 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
 Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* rc,
               const float* rep = nullptr, int64_t m_rep = 0, int64_t n_rep = 0) {
   const int64_t cls = n_class(n);
-  if (!autotune) return Plan{default_scheme(n), env_int("KTAU_TILE_Q", default_q(n)), 0.0};
+  if (!autotune) return Plan{default_scheme(n), default_q(n), 0.0};
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_tuned.find(cls);
   if (it == g_tuned.end()) {
@@ -240,13 +246,21 @@ int enqueue_batch(ktau_batch* b, hipStream_t s) {
     if (d.n > kLdsSortMax &&
         launch_prepass(d.X, d.m, d.n, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
                        (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
-                       (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, true,
-                       d.sort_tmp, s) != hipSuccess)
+                       (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status,
+                       ws_doubled(d.n), d.sort_tmp, s) != hipSuccess)
       return KTAU_EDEVICE;
-  for (const ClassRun& c : b->classes)
+  for (const ClassRun& c : b->classes) {
+    if (is_merge(c.scheme)) {
+      // long rows: a workgroup per pair already fills the device, one launch
+      // per matrix
+      for (int64_t p = c.first; p < c.first + c.count; ++p)
+        if (launch_pairs_merge(b->host_descs[p], s) != hipSuccess) return KTAU_EDEVICE;
+      continue;
+    }
     if (launch_pairs_persistent(c.scheme, b->descs + c.first, c.count, c.total_units, c.prefix,
                                 c.counters, b->words, s) != hipSuccess)
       return KTAU_EDEVICE;
+  }
   if (launch_tie_passes_batch(b->descs, b->count, b->max_n, s) != hipSuccess) return KTAU_EDEVICE;
   return KTAU_OK;
 }
@@ -375,7 +389,8 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
       d.unit_begin = acc;
       acc += d.n_units;
       uprefix.push_back(acc);
-      cr.work += (double)(mt.m * (mt.m - 1) / 2) * (double)scheme_capacity(pl.scheme);
+      cr.work += (double)(mt.m * (mt.m - 1) / 2) *
+                 (double)(is_merge(pl.scheme) ? mt.n : scheme_capacity(pl.scheme));
       rprefix[p + 1] = rprefix[p] + mt.m;
       b->host_descs[p] = d;
       b->max_n = std::max(b->max_n, (int)mt.n);
@@ -396,9 +411,11 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
   // query each class kernel's occupancy now, outside any capture
   for (ClassRun& c : b->classes) {
     if (rc != KTAU_OK) break;
-    if (launch_pairs_persistent(c.scheme, b->descs, 0, 0, nullptr, nullptr, b->words, s) !=
-        hipSuccess)
-      rc = KTAU_EDEVICE;
+    const hipError_t e =
+        is_merge(c.scheme)
+            ? prepare_pairs_merge(c.scheme)
+            : launch_pairs_persistent(c.scheme, b->descs, 0, 0, nullptr, nullptr, b->words, s);
+    if (e != hipSuccess) rc = KTAU_EDEVICE;
   }
   if (rc != KTAU_OK) {
     free_batch(b);

@@ -19,18 +19,31 @@ constexpr size_t kAlign = 256;
 
 // Longest row whose 64-bit sort keys one workgroup sorts in LDS (128 KB);
 // longer rows (up to KTAU_MAX_N) finish their sort in global scratch, one
-// 2 * kLdsSortMax-word slot per workgroup of at most kSortSlots.
+// slot of sort_slot_words(n) words (n rounded up to a power of two) per
+// workgroup of at most kSortSlots.
 constexpr int kLdsSortMax = 16384;
 constexpr int64_t kSortSlots = 256;
+
+// Rows of up to kDoubledMaxN samples keep doubled 16-bit ranks and sample
+// byte offsets in a pair workspace (2 rank + tag fits 16 bits); longer rows
+// keep them plain (16-bit ranks and sample indices up to 65535).
+constexpr int64_t kDoubledMaxN = 32768;
+__host__ __device__ inline bool ws_doubled(int64_t n) { return n <= kDoubledMaxN; }
 
 __host__ __device__ inline int64_t row_ld(int64_t n) {
   return (n + kRowAlign - 1) / kRowAlign * kRowAlign;
 }
 
+__host__ __device__ inline int64_t sort_slot_words(int64_t n) {
+  int64_t w = 2 * kLdsSortMax;
+  while (w < n) w <<= 1;
+  return w;
+}
+
 // Bytes of sort scratch the pre-pass of m rows of length n needs.
 inline size_t sort_scratch_bytes(int64_t m, int64_t n) {
   if (n <= kLdsSortMax) return 0;
-  return (size_t)(m < kSortSlots ? m : kSortSlots) * 2 * kLdsSortMax * sizeof(uint64_t);
+  return (size_t)(m < kSortSlots ? m : kSortSlots) * (size_t)sort_slot_words(n) * sizeof(uint64_t);
 }
 
 // Sort keys: padding slots beyond n, and the sentinel read past a run end.
@@ -81,13 +94,17 @@ __host__ __device__ inline void tile_coord(int64_t w, int64_t t, int64_t& yq, in
 // ---- device views
 
 struct RankView {
-  const uint16_t* perm;     // [rows][ld] sorted position -> 2 x sample (byte offset in a rank row)
-  const uint16_t* rank;     // [rows][ld] sample -> 2 x dense rank
+  // [rows][ld] sorted position -> 2 x sample (byte offset in a rank row), or
+  // the sample itself in rows longer than kDoubledMaxN
+  const uint16_t* perm;
+  // [rows][ld] sample -> 2 x dense rank, or the rank itself in rows longer
+  // than kDoubledMaxN
+  const uint16_t* rank;
   const uint16_t* rstart;   // [rows][ld] sorted position -> first position of its tie run
   const int64_t* n1;        // [rows]
   const int32_t* nruns;     // [rows] number of tie runs of length >= 2
   // [rows][ld/2] tie runs of length >= 2 in sorted order: bits 0-15 start,
-  // 16-31 length, 32-63 number of within-run pairs of the earlier runs
+  // 16-31 length - 1, 32-63 number of within-run pairs of the earlier runs
   const uint64_t* runs;
   int64_t ld;               // row stride in elements (runs: ld/2 per row)
 };
@@ -126,18 +143,29 @@ struct PairOut {
   X(kBlockK64, 64, 256)         \
   X(kBlockK128, 128, 256)
 
+// After the network schemes come the merge schemes for long rows
+// (ktau_merge.hip): one workgroup of up to 16 waves per pair, each wave
+// sorting and counting a chunk of 64 K keys with the network above (K = 32 or
+// 64), the levels above the chunks counted by a merge path over the keys in
+// LDS.  Capacity 16 chunks (32768 or 65536 samples).
 enum Scheme : int32_t {
 #define KTAU_ENUM(S, K, G) S,
   KTAU_FOR_EACH_SCHEME(KTAU_ENUM)
 #undef KTAU_ENUM
+  kNumNetSchemes,
+  kMergeK32 = kNumNetSchemes,
+  kMergeK64,
   kNumSchemes
 };
+constexpr int kMergeMaxWaves = 16;
 
+__host__ __device__ inline bool is_merge(int s) { return s == kMergeK32 || s == kMergeK64; }
 inline int scheme_lanes(int s) {
   static const int g[] = {
 #define KTAU_G(S, K, G) G,
       KTAU_FOR_EACH_SCHEME(KTAU_G)
 #undef KTAU_G
+      64 * kMergeMaxWaves, 64 * kMergeMaxWaves,
   };
   return g[s];
 }
@@ -146,12 +174,16 @@ inline int scheme_k(int s) {
 #define KTAU_K(S, K, G) K,
       KTAU_FOR_EACH_SCHEME(KTAU_K)
 #undef KTAU_K
+      32, 64,
   };
   return k[s];
 }
 inline int64_t scheme_capacity(int s) { return (int64_t)scheme_lanes(s) * scheme_k(s); }
 const char* scheme_name(int s);
 int default_scheme(int64_t n);
+// The fastest network scheme that holds n (n <= 32768): the scheme of the
+// query and permutation-test kernels, which have no merge form.
+int network_scheme(int64_t n);
 // Default tile edge: 8 up to n = 4096; longer rows take one 256-lane block per
 // pair and are few (m is small next to n), so smaller tiles spread them.
 int default_q(int64_t n);
@@ -219,6 +251,13 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
 // [J_begin, J_end), then the heavy-row pass and the composite pass.
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s);
 
+// Merge-scheme pair kernel over jobs [J_begin, J_end) of one matrix (pairs of
+// two heavy rows are left to the composite pass, as in the network schemes).
+hipError_t launch_pairs_merge(const MatDesc& d, hipStream_t s);
+// Sets a merge scheme kernel's LDS limit (done by its first launch too; call
+// it before capturing a launch into a graph).
+hipError_t prepare_pairs_merge(int scheme);
+
 // Persistent launch of one scheme over the tiles of the matrices of a
 // descriptor table (all of that scheme), taking tiles from the kXcds (8)
 // zeroed int64 counters at counters_dev.
@@ -243,7 +282,6 @@ struct WsLayout {
 };
 WsLayout ws_layout(int64_t m, int64_t n);
 int check_shape(int64_t m, int64_t n);
-int env_int(const char* name, int dflt);
 // Descriptor of a matrix whose rank pre-pass lives in `ws`; status NULL means
 // the status word at the start of ws.
 MatDesc matdesc(void* ws, int64_t m, int64_t n, const ktau_pair_out& out, int scheme, int q,

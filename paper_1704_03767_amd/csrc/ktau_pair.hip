@@ -307,14 +307,14 @@ const char* scheme_name(int s) {
                                 "block_k8",  "block_k16", "sub8_k16",  "sub16_k16", "sub16_k32",
                                 "sub16_k64", "sub32_k32", "sub32_k64", "wave_k32",  "wave_k64",
                                 "sub8_k32",  "sub8_k64",  "block_k32", "block_k64",
-                                "block_k128"};
+                                "block_k128", "merge_k32", "merge_k64"};
   static_assert(sizeof(names) / sizeof(names[0]) == kNumSchemes, "one name per scheme");
   return (s >= 0 && s < kNumSchemes) ? names[s] : "invalid";
 }
 
-// Fastest scheme per capacity class on MI355X (measured: the smallest group
-// whose network fits, within the LDS each in-flight pair needs).
-int default_scheme(int64_t n) {
+// Fastest network scheme per capacity class on MI355X (measured: the smallest
+// group whose network fits, within the LDS each in-flight pair needs).
+int network_scheme(int64_t n) {
   if (n <= 128) return kSub8K16;
   if (n <= 256) return kSub8K32;
   if (n <= 512) return kSub16K32;
@@ -326,6 +326,10 @@ int default_scheme(int64_t n) {
   return kBlockK128;
 }
 
+// Up to 4096 samples a whole pair fits one wave's network; longer rows take
+// the merge scheme (chunks of 4096 on a network, merge path above them).
+int default_scheme(int64_t n) { return n <= 4096 ? network_scheme(n) : kMergeK64; }
+
 int default_q(int64_t n) { return n <= 4096 ? 8 : n <= 16384 ? 4 : 2; }
 
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
@@ -334,6 +338,8 @@ hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
   case S: e = tiles ? launch_tiles_t<K, G>(d, s) : launch_jobs_t<K, G>(d, s); break;
   switch (d.scheme) {
     KTAU_FOR_EACH_SCHEME(KTAU_CASE)
+    case kMergeK32:
+    case kMergeK64: e = launch_pairs_merge(d, s); break;
     default: return hipErrorInvalidValue;
   }
 #undef KTAU_CASE

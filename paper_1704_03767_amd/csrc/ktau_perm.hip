@@ -186,9 +186,9 @@ hipError_t launch_perm_t(const PermDesc& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The default scheme of n (each capacity class's measured fastest).
+// The network scheme of n (each capacity class's measured fastest).
 hipError_t launch_perm(const PermDesc& d, hipStream_t s) {
-  switch (default_scheme(d.n)) {
+  switch (network_scheme(d.n)) {
     case kSub8K16: return launch_perm_t<16, 8>(d, s);
     case kSub8K32: return launch_perm_t<32, 8>(d, s);
     case kSub16K32: return launch_perm_t<32, 16>(d, s);
@@ -218,7 +218,7 @@ using namespace ktau;
 extern "C" {
 
 size_t ktau_perm_workspace_size(int64_t m, int64_t n, int64_t B) {
-  if (check_shape(m, n) != KTAU_OK || B < 1) return 0;
+  if (check_shape(m, n) != KTAU_OK || n > KTAU_MAX_N_NETWORK || B < 1) return 0;
   return perm_pad_offset(m, n) + 2 * perm_table_bytes(n, B);
 }
 
@@ -227,6 +227,7 @@ int ktau_perm_test(const float* X, int64_t m, int64_t n, const uint16_t* perms, 
                    size_t ws_bytes, void* stream) {
   int rc = check_shape(m, n);
   if (rc != KTAU_OK) return rc;
+  if (n > KTAU_MAX_N_NETWORK) return KTAU_ERANGE;
   if (!X || !perms || !count_out || B < 1 || B > (int64_t)0x7fffffff) return KTAU_EINVAL;
   if (!ws || ((uintptr_t)ws) % kAlign != 0) return KTAU_EINVAL;
   if (ws_bytes < ktau_perm_workspace_size(m, n, B)) return KTAU_ENOMEM;

@@ -9,11 +9,11 @@
 // One 256-thread workgroup per row.  The row's (value key, sample) pairs are
 // bitonic-sorted in LDS as 64-bit words (order-preserving 32-bit key << 16 |
 // sample), then block scans produce dense ranks and run starts.  Rows longer
-// than 16384 samples sort their halves in LDS and run part of the last merge
-// level in a global scratch slot.  Into a pair
-// workspace the sample indices and ranks are written doubled (byte offsets
-// into a rank row, and ranks with a free low bit for the pair network's
-// tag); the rank entry point writes them plain.
+// than 16384 samples sort blocks of 16384 in LDS and run the stages that span
+// blocks in a global scratch slot.  Into a pair workspace of rows up to 32768
+// samples the sample indices and ranks are written doubled (byte offsets into
+// a rank row, and ranks with a free low bit for the pair network's tag);
+// longer rows, and the rank entry point, get them plain.
 #include <limits.h>
 
 #include "ktau_internal.h"
@@ -206,11 +206,11 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
     if (prow) prow[k] = (uint16_t)(k << dbl);
     if (srow) srow[k] = (uint16_t)k;
   }
-  // Tail positions n..ld-1 map to themselves and rank 0x7FFF (doubled in a
-  // workspace), at or above every real rank, so the pair kernels gather
-  // padding keys without a bounds test.
+  // Tail positions n..ld-1 map to themselves and a padding rank at or above
+  // every real rank (0xFFFE doubled, 0xFFFF plain), so the pair kernels
+  // gather padding keys without a bounds test.
   if (rrow)
-    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)(0x7FFF << dbl);
+    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)(dbl ? 0xFFFEu : 0xFFFFu);
   atomicAdd(&s_n1, ties);
   __syncthreads();
   if (tid == 0) {
@@ -227,13 +227,15 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
     while (e < k0 + chunk && e < n && key_at(e) == key_at(k)) ++e;
     return e == k0 + chunk && e < n ? next_start : e;
   };
+  // (pair counts below n(n-1)/2 < 2^31 for n <= 65536; products in 64 bits)
+  auto run_pairs = [](int len) { return (int)((int64_t)len * (len - 1) / 2); };
   int my_runs = 0, my_pairs = 0;
   for (int c = 0; c < chunk; ++c) {
     const int k = k0 + c;
     if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
       const int len = run_end(k) - k;
       ++my_runs;
-      my_pairs += len * (len - 1) / 2;
+      my_pairs += run_pairs(len);
     }
   }
   int total_runs, total_pairs;
@@ -244,9 +246,10 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
     const int k = k0 + c;
     if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
       const int len = run_end(k) - k;
+      // entry: start (bits 0-15), length - 1 (16-31), earlier pairs (32-63)
       rrow_runs[run_idx++] =
-          ((uint64_t)(uint32_t)pairs << 32) | ((uint64_t)len << 16) | (uint64_t)k;
-      pairs += len * (len - 1) / 2;
+          ((uint64_t)(uint32_t)pairs << 32) | ((uint64_t)(len - 1) << 16) | (uint64_t)k;
+      pairs += run_pairs(len);
     }
   }
   if (tid == 0 && nruns) nruns[row] = total_runs;
@@ -267,11 +270,12 @@ __device__ __forceinline__ void prepass_row(const float* __restrict__ X, int64_t
   rank_outputs(s_keys, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, dbl);
 }
 
-// A row longer than kLdsSortMax (H), sorted as 2H words: each half is sorted
-// in LDS (the first ascending, the second descending, as the last level
-// wants them) and kept in this workgroup's global slot g (2H words); the last
-// level's first stage pairs the halves there, the rest of it runs per half in
-// LDS again, and the passes read the sorted words from the slot.
+// A row longer than kLdsSortMax (H), sorted as npow2 = 2H or 4H words in this
+// workgroup's global slot g.  Blocks of H are sorted in LDS (block b
+// ascending iff b is even, as the next level wants them) and stored in the
+// slot; every later level runs its stages of distance H and more over the
+// whole slot, and its stages below H per block in LDS again.  The passes then
+// read the sorted words from the slot.
 __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, int64_t row, int n,
                                  uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                                  uint16_t* __restrict__ rstart, int64_t ld,
@@ -281,31 +285,41 @@ __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, in
                                  int dbl) {
   constexpr int H = kLdsSortMax;
   const float* x = X + row * (int64_t)n;
-  for (int h = 0; h < 2; ++h) {
-    if (load_keys(x, n, h * H, H, s_keys)) {
+  int npow2 = 2 * H;
+  while (npow2 < n) npow2 <<= 1;
+  for (int b = 0; b < npow2 / H; ++b) {
+    if (load_keys(x, n, b * H, H, s_keys)) {
       if (threadIdx.x == 0) atomicExch(status, KTAU_ENAN);
       return;
     }
-    bitonic_stages(s_keys, H, h * H, 2, H, 1);
-    for (int i = threadIdx.x; i < H; i += kThreads) g[h * H + i] = s_keys[i];
+    bitonic_stages(s_keys, H, b * H, 2, H, 1);
+    for (int i = threadIdx.x; i < H; i += kThreads) g[b * H + i] = s_keys[i];
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < H; i += kThreads) {
-    const uint64_t a = g[i], b = g[H + i];
-    if (a > b) {
-      g[i] = b;
-      g[H + i] = a;
+  for (int k = 2 * H; k <= npow2; k <<= 1) {
+    for (int j = k >> 1; j >= H; j >>= 1) {
+      for (int i = threadIdx.x; i < npow2; i += kThreads) {
+        const int p = i ^ j;
+        if (p > i) {
+          const uint64_t a = g[i], c = g[p];
+          const bool up = (i & k) == 0;
+          if ((a > c) == up) {
+            g[i] = c;
+            g[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int b = 0; b < npow2 / H; ++b) {
+      for (int i = threadIdx.x; i < H; i += kThreads) s_keys[i] = g[b * H + i];
+      __syncthreads();
+      bitonic_stages(s_keys, H, b * H, k, k, H >> 1);
+      for (int i = threadIdx.x; i < H; i += kThreads) g[b * H + i] = s_keys[i];
+      __syncthreads();
     }
   }
-  __syncthreads();
-  for (int h = 0; h < 2; ++h) {
-    for (int i = threadIdx.x; i < H; i += kThreads) s_keys[i] = g[h * H + i];
-    __syncthreads();
-    bitonic_stages(s_keys, H, h * H, 2 * H, 2 * H, H >> 1);
-    for (int i = threadIdx.x; i < H; i += kThreads) g[h * H + i] = s_keys[i];
-    __syncthreads();
-  }
-  rank_outputs(g, row, n, 2 * H, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, dbl);
+  rank_outputs(g, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, dbl);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -322,7 +336,7 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
 }
 
 // Long rows: a grid of at most kSortSlots workgroups, each with its own
-// scratch slot of 2 kLdsSortMax words, strides over the rows.
+// scratch slot of sort_slot_words(n) words, strides over the rows.
 __global__ void __launch_bounds__(kThreads)
 prepass_long_kernel(const float* __restrict__ X, int64_t m, int n, uint16_t* __restrict__ perm,
                     uint16_t* __restrict__ rank, uint16_t* __restrict__ rstart, int64_t ld,
@@ -330,7 +344,7 @@ prepass_long_kernel(const float* __restrict__ X, int64_t m, int n, uint16_t* __r
                     int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
                     int32_t* __restrict__ status, uint64_t* __restrict__ scratch, int dbl) {
   extern __shared__ uint64_t s_keys[];
-  uint64_t* g = scratch + (int64_t)blockIdx.x * 2 * kLdsSortMax;
+  uint64_t* g = scratch + (int64_t)blockIdx.x * sort_slot_words(n);
   for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
     prepass_row_long(X, row, n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
                      s_keys, g, dbl);

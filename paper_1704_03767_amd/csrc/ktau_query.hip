@@ -337,19 +337,18 @@ using namespace ktau;
 
 extern "C" {
 
-int ktau_db_create(const float* X, int64_t m, int64_t n, void* stream, ktau_db** out) {
+int ktau_db_create_ex(const float* X, int64_t m, int64_t n, int scheme, void* stream,
+                      ktau_db** out) {
   if (!out || !X) return KTAU_EINVAL;
   *out = nullptr;
   if (m < 1 || n < 2 || m > (int64_t)0x7fffffff) return KTAU_EINVAL;
-  if (n > KTAU_MAX_N) return KTAU_ERANGE;
+  if (n > KTAU_MAX_N_NETWORK) return KTAU_ERANGE;
+  if (scheme >= 0 && (scheme >= kNumNetSchemes || scheme_capacity(scheme) < n)) return KTAU_EINVAL;
   const hipStream_t s = (hipStream_t)stream;
   ktau_db* db = new ktau_db();
   db->v.m = m;
   db->v.n = n;
-  // KTAU_FORCE_SCHEME (tests, tuning) picks another scheme that holds n
-  db->v.scheme = env_int("KTAU_FORCE_SCHEME", default_scheme(n));
-  if (db->v.scheme < 0 || db->v.scheme >= kNumSchemes || scheme_capacity(db->v.scheme) < n)
-    db->v.scheme = default_scheme(n);
+  db->v.scheme = scheme >= 0 ? scheme : network_scheme(n);
   const WsLayout L = ws_layout(m, n);
   if (hipMalloc(&db->ws, L.total) != hipSuccess) {
     delete db;
@@ -381,6 +380,10 @@ int ktau_db_create(const float* X, int64_t m, int64_t n, void* stream, ktau_db**
   }
   *out = db;
   return KTAU_OK;
+}
+
+int ktau_db_create(const float* X, int64_t m, int64_t n, void* stream, ktau_db** out) {
+  return ktau_db_create_ex(X, m, n, -1, stream, out);
 }
 
 void ktau_db_destroy(ktau_db* db) {

@@ -13,7 +13,9 @@
 //     slots and memory free up, and their work overlaps on the device;
 //   * a request flagged for a forced failure always runs alone;
 //   * a launch whose start fails part-way is drained (the executor waits for
-//     what it already enqueued) before its memory returns to the pool.
+//     what it already enqueued) before its memory returns to the pool;
+//   * while paused, nothing new is admitted (running launches still finish and
+//     requests still queue).
 #pragma once
 
 #include <stdint.h>
@@ -137,6 +139,9 @@ class Scheduler {
 
   void enqueue(Request* r) { queue_.push_back(r); }
 
+  void set_paused(bool p) { paused_ = p; }
+  bool paused() const { return paused_; }
+
   // Removes a queued request; false if it is not waiting.
   bool cancel(Request* r) {
     for (auto it = queue_.begin(); it != queue_.end(); ++it)
@@ -169,7 +174,7 @@ class Scheduler {
       --running_;
     }
     for (;;) {
-      if (queue_.empty()) break;
+      if (queue_.empty() || paused_) break;
       int free_slot = -1;
       for (int s = 0; s < (int)slots_.size(); ++s)
         if (!slots_[s]) {
@@ -247,6 +252,7 @@ class Scheduler {
   std::deque<Request*> queue_;
   std::vector<std::unique_ptr<Launch>> slots_;
   int64_t running_ = 0;
+  bool paused_ = false;
   Stats stats_;
 };
 

@@ -185,7 +185,9 @@ void worker_loop(ktau_server* s) {
     if (s->sched->running() > 0)
       s->cv_work.wait_for(lk, std::chrono::microseconds(20));
     else
-      s->cv_work.wait(lk, [&] { return s->stop || s->sched->queued() > 0; });
+      s->cv_work.wait(lk, [&] {
+        return s->stop || (s->sched->queued() > 0 && !s->sched->paused());
+      });
   }
 }
 
@@ -315,6 +317,16 @@ int ktau_server_inject_failure(ktau_server* s, int64_t ticket) {
   return KTAU_OK;
 }
 
+int ktau_server_pause(ktau_server* s, int paused) {
+  if (!s) return KTAU_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->sched->set_paused(paused != 0);
+  }
+  s->cv_work.notify_all();
+  return KTAU_OK;
+}
+
 int ktau_server_stats(ktau_server* s, ktau_server_counters* out) {
   if (!s || !out) return KTAU_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
@@ -339,6 +351,7 @@ void ktau_server_destroy(ktau_server* s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
+    s->sched->set_paused(false);   // what is queued is still served
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();

@@ -25,7 +25,8 @@ KTAU_EBUSY = -5
 KTAU_ENAN = -6
 KTAU_ECANCELED = -7
 KTAU_ETIMEDOUT = -8
-KTAU_MAX_N = 32768
+KTAU_MAX_N = 65536
+KTAU_MAX_N_NETWORK = 32768     # query search and permutation test
 KTAU_SCHEME_NAIVE = 100       # naive bit-set count, plain calls, n <= 256
 NAIVE_SCHEME_NAME = "naive_bits"
 

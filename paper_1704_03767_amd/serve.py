@@ -13,7 +13,7 @@ import ctypes
 import numpy as np
 import torch
 
-from .ktau import KTAU_OK, KtauError, _as_matrix, _check, _ptr, _stream, lib
+from .ktau import KTAU_OK, KtauError, _as_matrix, _check, _ptr, _stream, lib, scheme_id
 
 KTAU_MAX_K = 1024
 
@@ -49,6 +49,7 @@ def _slib():
     i64, i32, p, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
     decl = {
         "ktau_db_create": ([p, i64, i64, p, p], i32),
+        "ktau_db_create_ex": ([p, i64, i64, i32, p, p], i32),
         "ktau_db_destroy": ([p], None),
         "ktau_db_rows": ([p], i64),
         "ktau_db_samples": ([p], i64),
@@ -61,6 +62,7 @@ def _slib():
         "ktau_server_cancel": ([p, i64], i32),
         "ktau_server_inject_failure": ([p, i64], i32),
         "ktau_server_stats": ([p, p], i32),
+        "ktau_server_pause": ([p, i32], i32),
         "ktau_server_destroy": ([p], None),
         "ktau_server_launch_bytes": ([p, i64, i64], sz),
         "ktau_status": ([p, p], i32),
@@ -74,13 +76,19 @@ def _slib():
 
 
 class KtauDb:
-    """A database ranked once and kept resident in HBM (ktau_db_create)."""
+    """A database ranked once and kept resident in HBM (ktau_db_create; with
+    ``scheme`` given, ktau_db_create_ex and that network scheme)."""
 
-    def __init__(self, X: torch.Tensor, stream=None):
+    def __init__(self, X: torch.Tensor, stream=None, scheme=None):
         X = _as_matrix(X)
         h = ctypes.c_void_p()
-        _check(_slib().ktau_db_create(_ptr(X), X.shape[0], X.shape[1], _stream(stream),
-                                      ctypes.byref(h)), "ktau_db_create")
+        if scheme is None:
+            _check(_slib().ktau_db_create(_ptr(X), X.shape[0], X.shape[1], _stream(stream),
+                                          ctypes.byref(h)), "ktau_db_create")
+        else:
+            _check(_slib().ktau_db_create_ex(_ptr(X), X.shape[0], X.shape[1], scheme_id(scheme),
+                                             _stream(stream), ctypes.byref(h)),
+                   "ktau_db_create_ex")
         self._h = h
         self.m, self.n = X.shape
 
@@ -180,6 +188,10 @@ class KtauServer:
 
     def inject_failure(self, ticket: int) -> int:
         return int(_slib().ktau_server_inject_failure(self._h, ticket))
+
+    def pause(self, paused: bool = True) -> None:
+        """Stops or resumes admission of queued requests (ktau_server_pause)."""
+        _check(_slib().ktau_server_pause(self._h, 1 if paused else 0), "ktau_server_pause")
 
     def stats(self) -> dict:
         c = Counters()

@@ -67,6 +67,8 @@ void* st_create(int slots, long long max_batch, long long budget, long long per_
   return w;
 }
 
+void st_pause(void* p, int paused) { ((World*)p)->s->set_paused(paused != 0); }
+
 long long st_submit(void* p, long long nq, long long k, int force_fail) {
   World* w = (World*)p;
   if (!w->s->fits_ever(nq, k)) return -1;

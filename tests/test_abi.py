@@ -93,6 +93,14 @@ def test_host_side_argument_errors():
                             None) == K.KTAU_ERANGE
     assert L.ktau_perm_test(fake, 10, K.KTAU_MAX_N + 1, fake, 4, -1, -1, fake, None, fake,
                             need, None) == K.KTAU_ERANGE
+    # the permutation test and the query have network kernels only
+    assert L.ktau_perm_workspace_size(10, K.KTAU_MAX_N_NETWORK + 1, 4) == 0
+    assert L.ktau_perm_test(fake, 10, K.KTAU_MAX_N_NETWORK + 1, fake, 4, -1, -1, fake, None,
+                            fake, need, None) == K.KTAU_ERANGE
+    # rows up to KTAU_MAX_N are accepted by the all-pairs calls; their sort
+    # scratch covers n rounded up to a power of two
+    assert L.ktau_allpairs_workspace_size(10, K.KTAU_MAX_N) > 0
+    assert L.ktau_rank_workspace_size(3, 40000) >= 3 * 65536 * 8
     assert L.ktau_pair_to_job(10, 3, 3) == -1
     assert L.ktau_pair_to_job(10, 4, 3) == -1
     assert L.ktau_pair_to_job(10, 3, 10) == -1
@@ -103,9 +111,11 @@ def test_scheme_table():
     assert len(names) == K.lib().ktau_scheme_count()
     caps = [K.ktau_scheme_capacity(i) for i in range(len(names))]
     assert max(caps) >= K.KTAU_MAX_N
-    for n in (2, 64, 128, 129, 512, 1024, 1025, 4096, 4097, 8192, 8193, 16384):
+    for n in (2, 64, 128, 129, 512, 1024, 1025, 4096, 4097, 8192, 8193, 16384, 32769, 65536):
         s = K.ktau_default_scheme(n)
         assert caps[s] >= n
+    assert names[-2:] == ["merge_k32", "merge_k64"]
+    assert caps[-2:] == [32768, 65536]
     assert K.ktau_scheme_capacity(-1) == -1
 
 

@@ -49,7 +49,8 @@ def test_batch_matches_oracle_and_plain(use_graph, tmp_path):
 def test_batch_with_large_samples():
     # classes of 256-lane schemes next to small ones; the pre-pass and the
     # composite pass are sized by the largest n of the batch
-    shapes = [(21, 16384), (3, 9000), (40, 300), (2, 8192), (17, 4097), (9, 17941), (2, 32768)]
+    shapes = [(21, 16384), (3, 9000), (40, 300), (2, 8192), (17, 4097), (9, 17941), (2, 32768),
+              (3, 40000), (2, 65536)]
     mats = [synth.batch_matrix(s, 47, i) for i, s in enumerate(shapes)]
     mats[1][1] = np.floor(mats[1][1])                 # a heavily tied row
     mats[1][2] = np.round(mats[1][2])
@@ -71,7 +72,8 @@ def test_batch_forced_schemes():
     mats = _small_batch(10, 43)
     dev = [torch.from_numpy(X).cuda() for X in mats]
     want = [oracle.allpairs(X, "gse") for X in mats]
-    for scheme in ("block_k16", "block_k8", "wave_k64", "sub16_k64", "sub8_k16"):
+    for scheme in ("block_k16", "block_k8", "wave_k64", "sub16_k64", "sub8_k16", "merge_k32",
+                   "merge_k64"):
         small = [i for i, X in enumerate(mats) if X.shape[1] <= K.ktau_scheme_capacity(
             K.scheme_id(scheme))]
         b = K.KtauBatch([dev[i] for i in small], force_scheme=scheme, force_q=3)

@@ -70,6 +70,7 @@ def _oracle_rstart(order, rank):
 @pytest.mark.parametrize("shape_seed", [(64, 128, 1), (33, 1000, 2), (17, 4096, 3), (5, 2, 4),
                                         (6, 8193, 6), (5, 16384, 7), (4, 16385, 8),
                                         (6, 17941, 9), (3, 32768, 10),
+                                        (3, 32769, 11), (4, 40000, 12), (4, 65536, 13),
                                         (9, 65, 5)])
 def test_prepass_matches_oracle(shape_seed):
     m, n, seed = shape_seed
@@ -171,6 +172,70 @@ def test_large_sample_counts(n):
     for scheme in ALL_SCHEMES:
         if K.ktau_scheme_capacity(scheme) >= n:
             _check_full(X, scheme=scheme, q=2)
+
+
+# Rows longer than 32768 samples: plain 16-bit ranks in the workspace and the
+# merge scheme's two passes over the halves of the rank range.
+WIDE_N = [32769, 40000, 65535, 65536]
+
+
+@pytest.mark.parametrize("n", WIDE_N)
+def test_wide_sample_counts(n):
+    m = 10
+    X = _edge_matrix(m, n, 2000 + n)
+    X[7] = 5.0                                               # a second constant row
+    X[8] = np.round(np.random.default_rng(n).standard_normal(n), 2).astype(np.float32)
+    got = _check_full(X)
+    assert got["tau_b"][K.ktau_pair_to_job(m, 2, 4)] == 1.0
+    assert got["tau_b"][K.ktau_pair_to_job(m, 2, 3)] == -1.0
+    j = K.ktau_pair_to_job(m, 0, 7)                          # two constant rows
+    assert got["nd"][j] == 0 and got["n3"][j] == n * (n - 1) // 2
+    # a job sub-range through the same kernel
+    part = _np(K.ktau_allpairs_range(torch.from_numpy(X).cuda(), 5, 31))
+    for k in ("nc", "nd", "n3", "tau_b"):
+        assert np.array_equal(part[k], got[k][5:31], equal_nan=True), k
+
+
+@pytest.mark.parametrize("n", [32769, 65536])
+def test_wide_rank_halves_closed_forms(n):
+    # the counting passes split ranks at 32767 | 32768: pairs of samples on
+    # either side of the split, in both orders, against closed forms (a
+    # permutation pi of the samples against the identity has n_d = inv(pi))
+    base = np.arange(n, dtype=np.float32)
+    rows = [base]
+    swap = base.copy()
+    swap[[32767, 32768]] = swap[[32768, 32767]]              # one inversion at the split
+    rows.append(swap)
+    rows.append(base[::-1].copy())                            # n0 inversions
+    rot = np.roll(base, 1)                                    # n - 1 inversions
+    rows.append(rot)
+    blk = base.copy()                                         # upper half moved first
+    blk = np.concatenate([base[32768:], base[:32768]])
+    rows.append(blk)
+    X = np.stack(rows)
+    got = _gpu_allpairs(X)
+    n0 = n * (n - 1) // 2
+    hi = n - 32768
+    expect = {(0, 1): 1, (0, 2): n0, (0, 3): n - 1, (0, 4): 32768 * hi}
+    for (y, x), nd in expect.items():
+        j = K.ktau_pair_to_job(len(rows), y, x)
+        assert got["nd"][j] == nd, (y, x, got["nd"][j], nd)
+        assert got["nc"][j] == n0 - nd and got["n3"][j] == 0
+    want = oracle.allpairs(X, "gse")
+    _assert_same(got, want)
+
+
+@pytest.mark.parametrize("scheme", ["merge_k32", "merge_k64"])
+@pytest.mark.parametrize("n", [2, 100, 2048, 2049, 4096, 4097, 6143, 8192, 12289, 20000])
+def test_merge_schemes_every_chunk_count(scheme, n):
+    # one chunk (network only) up to many, each with a ragged last chunk
+    cap = K.ktau_scheme_capacity(K.scheme_id(scheme))
+    if n > cap:
+        pytest.skip("beyond the scheme's capacity")
+    X = _edge_matrix(9, n, 3000 + n)
+    _check_full(X, scheme=scheme)
+    Y = synth.lognormal_blocks(11, n, 70 + n % 5)
+    _check_full(Y, scheme=scheme)
 
 
 @pytest.mark.parametrize("n", [6000, 16384, 17941])

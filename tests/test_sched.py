@@ -31,6 +31,7 @@ def lib(tmp_path_factory):
         ("st_cancel", [p, ll], i), ("st_peak_running", [p], ll), ("st_destroy", [p], None),
         ("st_pool_fuzz", [ll, i, ctypes.c_uint], i), ("st_fail_start", [p, ll], None),
         ("st_overlaps", [p], i), ("st_abandoned", [p], i), ("st_inflight", [p], i),
+        ("st_pause", [p, i], None),
     ]:
         f = getattr(L, name)
         f.argtypes = args
@@ -157,4 +158,24 @@ def test_failed_start_is_drained_before_its_region_is_reused(lib):
     lib.st_finish_slot(w, 1)
     lib.st_step(w)
     assert lib.st_status(w, b) == 0 and lib.st_pool_used(w) == 0
+    lib.st_destroy(w)
+
+
+def test_pause_holds_admission_and_resume_merges(lib):
+    w = lib.st_create(2, 64, 1 << 30, 1000)
+    lib.st_pause(w, 1)
+    t = [lib.st_submit(w, nq, 100, 0) for nq in (2, 3, 4)]
+    lib.st_step(w)
+    assert [lib.st_state(w, x) for x in t] == [QUEUED] * 3 and lib.st_running(w) == 0
+    lib.st_pause(w, 0)
+    lib.st_step(w)
+    assert [lib.st_batch_requests(w, x) for x in t] == [3, 3, 3]
+    # a running launch still completes while admission is paused
+    lib.st_pause(w, 1)
+    u = lib.st_submit(w, 1, 100, 0)
+    lib.st_finish_slot(w, 0)
+    assert lib.st_step(w) == 3 and lib.st_state(w, u) == QUEUED
+    lib.st_pause(w, 0)
+    lib.st_step(w)
+    assert lib.st_state(w, u) == RUNNING
     lib.st_destroy(w)
