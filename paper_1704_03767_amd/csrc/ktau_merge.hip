@@ -47,13 +47,24 @@ constexpr int kMergeHdrWords = 64;          // LDS words before the row: sums, s
 constexpr uint32_t kMergeSentinel = 0xFFFFu;  // above every key (keys <= 0xFFFE)
 constexpr uint32_t kHalf = 32768;
 
+// While sorted runs are merged the row is kept padded: 4 uint16 (two LDS
+// dwords) after every 64 keys.  Each lane merges 64 consecutive outputs, so
+// lanes read keys 32 to 64 positions apart; unpadded, such strides (64 or
+// 128 bytes) put every lane of a wave on the same LDS bank.  Padded, a
+// stride of 32 keys moves 17 dwords (a different bank per lane) and one of 64
+// keys 34 dwords (two lanes per bank).  The in-order row of the gather and
+// the in-run count stays unpadded.
+__device__ __forceinline__ int padded(int p) { return p + ((p >> 6) << 2); }
+
 template <int K>
 struct MergeShape {
   static constexpr int kChunk = 64 * K;
   static int waves(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
-  // header, row, and 16 bytes of slack for the merge's reads one past a run
+  // header, padded row, and 16 bytes of slack for the merge's reads one past
+  // a run
   static size_t lds_bytes(int waves) {
-    return kMergeHdrWords * sizeof(uint32_t) + (size_t)waves * kChunk * sizeof(uint16_t) + 16;
+    const size_t keys = (size_t)waves * kChunk;
+    return kMergeHdrWords * sizeof(uint32_t) + (keys + keys / 16) * sizeof(uint16_t) + 16;
   }
 };
 
@@ -129,12 +140,19 @@ __device__ __forceinline__ void merge_gather(const uint16_t* row, const uint16_t
   }
 }
 
-// Stores keys in the network's packing at positions k0 .. k0+K-1 of the row.
+// K consecutive uint16 packed in K/2 words (element 2i low, 2i+1 high) to an
+// 8-byte aligned address, two words per store.
 template <int K>
-__device__ __forceinline__ void merge_store_keys(uint16_t* row, int k0, const u16x2 (&key)[K / 2],
-                                                 uint32_t mask) {
+__device__ __forceinline__ void store_words8(uint16_t* p, const uint32_t (&w)[K / 2]) {
+#pragma unroll
+  for (int i = 0; i < K / 4; ++i) ((uint2*)p)[i] = make_uint2(w[2 * i], w[2 * i + 1]);
+}
+
+// Keys in the network's packing, as K consecutive words in position order.
+template <int K>
+__device__ __forceinline__ void unpack_keys(const u16x2 (&key)[K / 2], uint32_t mask,
+                                            uint32_t (&w)[K / 2]) {
   constexpr int KV = K / 2;
-  uint32_t w[KV];
 #pragma unroll
   for (int i = 0; i < KV / 2; ++i) {
     const uint32_t lo = bitonic::bits(key[2 * i]) & mask;
@@ -143,32 +161,43 @@ __device__ __forceinline__ void merge_store_keys(uint16_t* row, int k0, const u1
     w[i] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
     w[KV / 2 + i] = __builtin_amdgcn_perm(hi, lo, 0x07060302u);
   }
+}
+
+// Stores keys in the network's packing at positions k0 .. k0+K-1 of the
+// unpadded row.
+template <int K>
+__device__ __forceinline__ void merge_store_keys(uint16_t* row, int k0, const u16x2 (&key)[K / 2],
+                                                 uint32_t mask) {
+  uint32_t w[K / 2];
+  unpack_keys<K>(key, mask, w);
   store_words<K>(row + k0, w);
 }
 
-// One lane's K outputs of the merge of sorted runs A = blk[0, lenA) and
-// B = blk[s, s + lenB), starting at output position diag; returns the number
-// of (A, B) pairs among them with the A key strictly larger (for each B key
-// taken, the A keys not yet taken).  With kStore the merged keys are packed
-// into w (output 2i low, 2i + 1 high).  Every step loads the next key of the
-// run it took from without a branch; a load one past the end of a run stays
-// inside the LDS row (runs are contiguous, and the row has slack after it)
-// and is replaced by the sentinel.
+// One lane's K outputs of the merge of sorted runs A (positions l0 ..
+// l0 + lenA - 1 of the padded row) and B (l0 + s .. l0 + s + lenB - 1),
+// starting at output position diag; returns the number of (A, B) pairs among
+// them with the A key strictly larger (for each B key taken, the A keys not
+// yet taken).  With kStore the merged keys are packed into w (output 2i low,
+// 2i + 1 high).  Every step loads the next key of the run it took from without
+// a branch; a load one past the end of a run stays inside the LDS row (runs
+// are contiguous, and the row has slack after it) and is replaced by the
+// sentinel.
 template <int K, bool kStore>
-__device__ __forceinline__ uint32_t merge_segment(const uint16_t* blk, int s, int lenA, int lenB,
-                                                  int diag, uint32_t (&w)[K / 2]) {
+__device__ __forceinline__ uint32_t merge_segment(const uint16_t* row, int l0, int s, int lenA,
+                                                  int lenB, int diag, uint32_t (&w)[K / 2]) {
+  auto at = [&](int p) { return (uint32_t)row[padded(l0 + p)]; };
   // merge path: the number of A keys among the first diag outputs
   int lo = diag > lenB ? diag - lenB : 0;
   int hi = diag < lenA ? diag : lenA;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (blk[mid] <= blk[s + diag - 1 - mid]) lo = mid + 1;
+    if (at(mid) <= at(s + diag - 1 - mid)) lo = mid + 1;
     else hi = mid;
   }
   int rem = lenA - lo;           // A keys not yet taken
   int ib = diag - lo;            // B keys taken
-  uint32_t a = rem > 0 ? (uint32_t)blk[lo] : kMergeSentinel;
-  uint32_t b = ib < lenB ? (uint32_t)blk[s + ib] : kMergeSentinel;
+  uint32_t a = rem > 0 ? at(lo) : kMergeSentinel;
+  uint32_t b = ib < lenB ? at(s + ib) : kMergeSentinel;
   uint32_t cnt = 0, low = 0;
 #pragma unroll
   for (int t = 0; t < K; ++t) {
@@ -184,7 +213,7 @@ __device__ __forceinline__ uint32_t merge_segment(const uint16_t* blk, int s, in
     if (t + 1 < K) {
       rem -= tb ? 0 : 1;
       ib += tb ? 1 : 0;
-      const uint32_t raw = blk[tb ? s + ib : lenA - rem];
+      const uint32_t raw = at(tb ? s + ib : lenA - rem);
       const int left = tb ? lenB - ib : rem;   // keys left in the run just read
       const uint32_t nv = left > 0 ? raw : kMergeSentinel;
       a = tb ? a : nv;
@@ -276,7 +305,12 @@ __device__ __forceinline__ uint32_t merge_count(u16x2 (&key)[K / 2], uint16_t* r
   if (active) share += Net::count(key, plane, nullptr);
   // the row may still be the staged rank row that other waves gather from
   __syncthreads();
-  if (active) merge_store_keys<K>(row, k0, key, 0xFFFEFFFEu);   // sorted, tags cleared
+  if (active) {
+    // sorted, tags cleared, into the padded row
+    uint32_t w[KV];
+    unpack_keys<K>(key, 0xFFFEFFFEu, w);
+    store_words8<K>(row + padded(k0), w);
+  }
   __syncthreads();
   for (int s = C; s < NR; s <<= 1) {
     const bool top = 2 * s >= NR;
@@ -287,11 +321,11 @@ __device__ __forceinline__ uint32_t merge_count(u16x2 (&key)[K / 2], uint16_t* r
     const bool work = active && lenB > 0;
     uint32_t w[KV];
     if (top) {
-      if (work) share += merge_segment<K, false>(row + l0, s, lenA, lenB, k0 - l0, w);
+      if (work) share += merge_segment<K, false>(row, l0, s, lenA, lenB, k0 - l0, w);
     } else {
-      if (work) share += merge_segment<K, true>(row + l0, s, lenA, lenB, k0 - l0, w);
+      if (work) share += merge_segment<K, true>(row, l0, s, lenA, lenB, k0 - l0, w);
       __syncthreads();
-      if (work) store_words<K>(row + k0, w);
+      if (work) store_words8<K>(row + padded(k0), w);
       __syncthreads();
     }
   }
@@ -396,28 +430,57 @@ __global__ void __launch_bounds__(kMergeThreads) merge_jobs_kernel(MatDesc d) {
   }
 }
 
-// Workgroups per launch: enough to keep every CU busy with a few pairs each
-// (pairs cost about the same, so a static stride balances them).
-constexpr int64_t kMergeGrid = 2048;
+// Workgroups a CU holds at once for each workgroup size (occupancy query,
+// cached), and the number of CUs.  A launch has twice as many workgroups as
+// the device holds, each striding over the jobs: the second half fills CUs
+// whose first workgroups finish early (pair costs vary with their ties);
+// measured 0-7% faster than exactly one full device.
+template <int K, bool kWide>
+struct MergeOccupancy {
+  int per_cu[kMergeMaxWaves + 1] = {};
+  int cus = 0;
+  hipError_t err = hipSuccess;
+  MergeOccupancy() {
+    int dev = 0;
+    err = hipGetDevice(&dev);
+    if (err == hipSuccess)
+      err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err == hipSuccess)
+      err = hipFuncSetAttribute(reinterpret_cast<const void*>(merge_jobs_kernel<K, kWide>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)MergeShape<K>::lds_bytes(kMergeMaxWaves));
+    for (int w = 1; w <= kMergeMaxWaves && err == hipSuccess; ++w) {
+      int v = 0;
+      err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &v, merge_jobs_kernel<K, kWide>, 64 * w, MergeShape<K>::lds_bytes(w));
+      per_cu[w] = v < 1 ? 1 : v;
+    }
+  }
+};
+
+// Set up on the first use, outside any graph capture (prepare_pairs_merge).
+template <int K, bool kWide>
+const MergeOccupancy<K, kWide>& merge_occupancy() {
+  static const MergeOccupancy<K, kWide> occ;
+  return occ;
+}
 
 template <int K, bool kWide>
 hipError_t merge_prepare_t() {
-  static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(merge_jobs_kernel<K, kWide>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)MergeShape<K>::lds_bytes(kMergeMaxWaves));
-  return attr;
+  return merge_occupancy<K, kWide>().err;
 }
 
 template <int K, bool kWide>
 hipError_t merge_launch_t(const MatDesc& d, hipStream_t s) {
   using Shape = MergeShape<K>;
-  const hipError_t attr = merge_prepare_t<K, kWide>();
-  if (attr != hipSuccess) return attr;
+  const MergeOccupancy<K, kWide>& occ = merge_occupancy<K, kWide>();
+  if (occ.err != hipSuccess) return occ.err;
   const int64_t count = d.J_end - d.J_begin;
   if (count < 1) return hipSuccess;
   const int waves = Shape::waves(d.n);
   if (waves < 1 || waves > kMergeMaxWaves) return hipErrorInvalidValue;
-  const int64_t grid = count < kMergeGrid ? count : kMergeGrid;
+  const int64_t fill = 2 * (int64_t)occ.cus * occ.per_cu[waves];
+  const int64_t grid = count < fill ? count : fill;
   hipLaunchKernelGGL((merge_jobs_kernel<K, kWide>), dim3((unsigned)grid), dim3(64 * waves),
                      Shape::lds_bytes(waves), s, d);
   return hipGetLastError();
