@@ -164,6 +164,21 @@ int ktau_allpairs_range(const float* X_dev, int64_t m, int64_t n,
                         int64_t J_begin, int64_t J_end, ktau_pair_out out,
                         void* workspace_dev, size_t ws_bytes, void* stream);
 
+/* ktau_allpairs for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation and results, with the workspace in a fixed static
+ * device array of 64 MiB inside the library (one per GPU, held until the
+ * process ends) instead of caller memory; the call makes no allocation.
+ * Shapes whose ktau_allpairs_workspace_size exceeds 64 MiB are refused with
+ * KTAU_ENOMEM before anything is enqueued (for example m = 4096, n = 1024
+ * fits; m = 16384, n = 1024 does not).  status_dev (device int32, may be
+ * NULL) receives the call's latched status (KTAU_ENAN for a NaN input, else
+ * KTAU_OK) in stream order.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams or threads) race and must be
+ * serialised by the caller.  Other errors as ktau_allpairs. */
+int ktau_allpairs_noalloc(const float* X_dev, int64_t m, int64_t n, ktau_pair_out out,
+                          int32_t* status_dev, void* stream);
+
 /* The two halves of ktau_allpairs, for callers that rank once and then make
  * several passes over job sub-ranges (Sec. 4.3) or time the halves apart.
  * ktau_prepare clears the workspace status and runs the rank pre-pass of X

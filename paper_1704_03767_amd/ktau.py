@@ -58,6 +58,7 @@ def _declare(lib):
         "ktau_rank_workspace_size": ([i64, i64], sz),
         "ktau_allpairs_workspace_size": ([i64, i64], sz),
         "ktau_allpairs": ([p, i64, i64, _PairOut, p, sz, p], i32),
+        "ktau_allpairs_noalloc": ([p, i64, i64, _PairOut, p, p], i32),
         "ktau_allpairs_range": ([p, i64, i64, i64, i64, _PairOut, p, sz, p], i32),
         "ktau_allpairs_ex": ([p, i64, i64, i64, i64, _PairOut, p, sz, i32, i32, p], i32),
         "ktau_status": ([p, p], i32),
@@ -285,6 +286,19 @@ def ktau_allpairs(X: torch.Tensor, out: dict | None = None, workspace: torch.Ten
         if st != KTAU_OK:
             raise KtauError(st, "ktau_allpairs")
     return out
+
+
+def ktau_allpairs_noalloc(X: torch.Tensor, out: dict, status: torch.Tensor | None = None,
+                          stream=None) -> None:
+    """ktau_allpairs_noalloc: all strict pairs into the caller's output
+    tensors with the library's static scratch (no allocation in the call;
+    out as from alloc_outputs).  status (a CUDA int32 tensor of one element)
+    receives the latched status in stream order."""
+    X = _as_matrix(X)
+    m, n = X.shape
+    _check(lib().ktau_allpairs_noalloc(_ptr(X), m, n, _pair_out(out),
+                                       _ptr(status) if status is not None else None,
+                                       _stream(stream)), "ktau_allpairs_noalloc")
 
 
 def ktau_perm_test(X: torch.Tensor, perms: torch.Tensor, J_begin: int = -1, J_end: int = -1,
