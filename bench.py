@@ -94,8 +94,11 @@ def cpu_model() -> str:
     return platform.processor() or platform.machine()
 
 
-def cpu_baseline(X, seconds: float, seed: int = 99) -> dict:
-    """The oracle (sorting kernel, all host threads) on a seeded sample of pairs."""
+def cpu_baseline(X, seconds: float, gpu: dict | None = None, seed: int = 99) -> dict:
+    """The oracle (sorting kernel, all host threads) on a seeded sample of
+    pairs.  With gpu (the timed run's device outputs: nc, nd, n3, tau_b by job
+    id and n1 per row) the first batch of sampled pairs is also compared with
+    them: the parity record of the run that was timed."""
     import numpy as np
 
     import oracle
@@ -103,26 +106,67 @@ def cpu_baseline(X, seconds: float, seed: int = 99) -> dict:
     m, n = X.shape
     threads = oracle.max_threads()
     rng = np.random.default_rng(seed)
+    parity = None
 
-    def run(count):
+    def run(count, check=False):
+        nonlocal parity
         ys = rng.integers(0, m - 1, count)
         xs = ys + 1 + (rng.integers(0, 1 << 62, count) % (m - 1 - ys))
         t0 = time.perf_counter()
-        oracle.pairs(X, ys, xs, "gse", threads)
-        return time.perf_counter() - t0
+        want = oracle.pairs(X, ys, xs, "gse", threads)
+        dt = time.perf_counter() - t0
+        if check and gpu is not None:
+            import torch
+
+            J = ys * (2 * (m - 1) - ys + 1) // 2 + (xs - 1 - ys)   # strict job ids
+            Jd = torch.from_numpy(J).to(gpu["nc"].device)
+            same = all(np.array_equal(gpu[k][Jd].cpu().numpy(), want[k])
+                       for k in ("nc", "nd", "n3"))
+            n1 = gpu["n1"].cpu().numpy()
+            same = same and np.array_equal(n1[ys], want["n1"]) and np.array_equal(n1[xs],
+                                                                                  want["n2"])
+            tg, tw = gpu["tau_b"][Jd].cpu().numpy(), want["tau_b"]
+            nan_same = bool(np.array_equal(np.isnan(tg), np.isnan(tw)))
+            ok = ~np.isnan(tw)
+            parity = {"pairs": int(count), "counts_equal": bool(same),
+                      "tau_nan_equal": nan_same,
+                      "max_abs_dtau": float(np.abs(tg[ok] - tw[ok]).max()) if ok.any() else 0.0,
+                      "what": "n_c, n_d, n3, n1, n2 and tau_B of the timed (batched) run at "
+                              "the oracle's first batch of seeded pairs"}
+        return dt
 
     # batches of seeded pairs, each sized from the rate so far, until about
     # `seconds` of oracle time have been spent
     count, dt, batch = 0, 0.0, max(threads * 64, 1024)
+    first = True
     while dt < seconds:
-        dt += run(batch)
+        dt += run(batch, check=first)
+        first = False
         count += batch
         left = seconds - dt
         batch = int(min(20_000_000, max(threads * 64, 1.1 * left * count / max(dt, 1e-6))))
-    return {"value": count / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{count} seeded random strict pairs of the same matrix, "
-                      f"sorting-kernel routine, {dt:.1f} s on {threads} threads",
-            "cpu": cpu_model(), "nproc": os.cpu_count()}
+    res = {"value": count / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+           "sample": f"{count} seeded random strict pairs of the same matrix, "
+                     f"sorting-kernel routine, {dt:.1f} s on {threads} threads",
+           "cpu": cpu_model(), "nproc": os.cpu_count()}
+    if parity is not None:
+        res["parity"] = parity
+    return res
+
+
+def outputs_equal(a: dict, b: dict) -> bool:
+    """Bitwise equality of two device output sets (NaN tau_B at the same
+    slots)."""
+    import torch
+
+    for k in ("nc", "nd", "n3", "n1"):
+        if k in a and k in b and not torch.equal(a[k], b[k]):
+            return False
+    ta, tb = a["tau_b"], b["tau_b"]
+    if not torch.equal(ta.isnan(), tb.isnan()):
+        return False
+    ok = ~ta.isnan()
+    return bool(torch.equal(ta[ok], tb[ok]))
 
 
 def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
@@ -135,6 +179,8 @@ def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
     del mats
     outs = [K.alloc_outputs(X.shape[0] * (X.shape[0] - 1) // 2, X.shape[0], X.device)
             for X in dev]
+    outs_b = [K.alloc_outputs(X.shape[0] * (X.shape[0] - 1) // 2, X.shape[0], X.device)
+              for X in dev]
     pairs = sum(X.shape[0] * (X.shape[0] - 1) // 2 for X in dev)
     steps = sum(X.shape[0] * (X.shape[0] - 1) // 2 * merge_steps(X.shape[1]) for X in dev)
     ws = torch.empty(max(K.ktau_allpairs_workspace_size(*X.shape) for X in dev),
@@ -160,18 +206,20 @@ def uneven_batch(K, synth, torch, stream, reps: int) -> dict:
     ms_plain = timed(plain)
     if K.ktau_status(ws) != K.KTAU_OK:
         raise RuntimeError("uneven batch: plain calls failed")
-    plan = K.KtauBatch(dev, outs=outs, stream=stream)
+    plan = K.KtauBatch(dev, outs=outs_b, stream=stream)
     ms_batch = timed(lambda: plan.run(stream))
     if plan.status(stream) != K.KTAU_OK:
         raise RuntimeError("uneven batch: batched run failed")
     classes = sorted({plan.plan(i) for i in range(len(dev))})
     plan.close()
+    same = all(outputs_equal(a, b) for a, b in zip(outs, outs_b))
     return {"workload": "256 matrices m~U[32,2048] n~U[64,4096], 20% of entries on a 0.25 grid, "
                         "seed 4",
             "pairs": pairs, "merge_steps": steps,
             "plain_ms": ms_plain, "plain_pairs_per_s": pairs / (ms_plain * 1e-3),
             "batched_ms": ms_batch, "batched_pairs_per_s": pairs / (ms_batch * 1e-3),
             "speedup": ms_plain / ms_batch,
+            "batched_equals_plain": same,
             "plans": [f"{s}/q{q}" for s, q in classes]}
 
 
@@ -208,17 +256,101 @@ def plain_timing(K, torch, stream, X, reps: int) -> dict:
             "merge_steps_per_s": P * merge_steps(n) / (ms * 1e-3)}
 
 
+def split_timing(K, torch, stream, X, reps: int, scheme=None) -> dict:
+    """The plain path on matrix X with the pre-pass and the pair kernel timed
+    apart (HIP events on the launching stream); outputs in HBM."""
+    import numpy as np
+
+    Xd = torch.from_numpy(X).cuda()
+    m, n = X.shape
+    P = m * (m - 1) // 2
+    out = K.alloc_outputs(P, m, Xd.device)
+    ws = K.alloc_workspace(m, n, Xd.device)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps + 1)]
+    for e in ev:
+        e[0].record(stream)
+        K.ktau_prepare(Xd, ws, out["n1"], stream=stream)
+        e[1].record(stream)
+        K.ktau_pairs(m, n, out, ws, scheme=scheme, stream=stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    if K.ktau_status(ws) != K.KTAU_OK:
+        raise RuntimeError(f"plain call on {m} x {n} failed")
+    prep = [e[0].elapsed_time(e[1]) for e in ev[1:]]
+    pair = [e[1].elapsed_time(e[2]) for e in ev[1:]]
+    ms = float(np.mean(prep)) + float(np.mean(pair))
+    pair_ms = float(np.mean(pair))
+    steps = P * merge_steps(n)
+    used = K.ktau_plain_default_scheme(n) if scheme is None else K.scheme_id(scheme)
+    return {"m": m, "n": n, "pairs": P, "ms": ms, "pairs_per_s": P / (ms * 1e-3),
+            "prepass_ms": float(np.mean(prep)), "pair_kernel_ms": pair_ms,
+            "pair_kernel_ms_min": float(np.min(pair)),
+            "scheme": scheme_label(K, used),
+            "merge_steps_per_s": steps / (pair_ms * 1e-3),
+            "frac": steps / (pair_ms * 1e-3) / INT_VALU_OPS, "out": out}
+
+
+def medium(K, synth, torch, stream, reps: int) -> dict:
+    """The medium workload: m = 4096 x n = 512 from a latent-factor model (8
+    factors, noise sd 0.5), 10% of the rows quantised to 16 levels (seed 2):
+    the plain path (pre-pass and pair kernel apart) and the batched form,
+    whose results must equal the plain call's bit for bit."""
+    X = synth.config_matrix(2)
+    r = split_timing(K, torch, stream, X, reps)
+    plain_out = r.pop("out")
+    Xd = torch.from_numpy(X).cuda()
+    m = X.shape[0]
+    out_b = K.alloc_outputs(m * (m - 1) // 2, m, Xd.device)
+    plan = K.KtauBatch([Xd], outs=[out_b], stream=stream)
+    plan.run(stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    if plan.status(stream) != K.KTAU_OK:
+        raise RuntimeError("medium: batched run failed")
+    ms_b = e0.elapsed_time(e1) / reps
+    r["batched"] = {"ms": ms_b, "pairs_per_s": r["pairs"] / (ms_b * 1e-3),
+                    "scheme": plan.plan(0)[0], "q": plan.plan(0)[1],
+                    "equals_plain": outputs_equal(out_b, plain_out)}
+    plan.close()
+    r["workload"] = ("medium m=4096 n=512 latent factors (8, noise sd 0.5), 10% of rows "
+                     "quantised to 16 levels, seed 2")
+    r["ops_per_pair"] = merge_steps(X.shape[1])
+    r["input_sha256"] = synth.sha256(X)[:16]
+    return r
+
+
+def large_n(K, synth, torch, stream, reps: int) -> dict:
+    """Rows beyond one wave's network: the merge scheme (chunk networks and a
+    merge path over them) on log-normal rows of 32768 and 65536 samples (the
+    second with plain 16-bit ranks counted in two halves)."""
+    rows = []
+    for m, n in ((200, 32768), (96, 65536)):
+        r = split_timing(K, torch, stream, synth.lognormal_blocks(m, n, 3), reps)
+        r.pop("out")
+        r["workload"] = (f"m={m} n={n} log-normal, blocks of 64 rows at rho=0.6, 2% exact zeros, "
+                         "seed 3")
+        rows.append(r)
+    return {"rows": rows}
+
+
 def other_shapes(K, synth, torch, stream, reps: int) -> dict:
     """The paper's two orientations of its gene-expression data: genes as
     variables (m = 17,941, n = 353, as its timed datasets; its one-Phi VSE
     rate for that shape, derived from Table 4, is context) and samples as
-    variables (m = 353, n = 17,941, beyond the 16-bit rank packing of the
-    fast merge until 32,768)."""
+    variables (m = 353, n = 17,941: the merge scheme, pre-pass and pair kernel
+    timed apart)."""
     genes = plain_timing(K, torch, stream, synth.lognormal_blocks(17941, 353, 7), reps)
     genes["workload"] = ("gene-vs-gene m=17941 n=353 log-normal, blocks of 64 rows at rho=0.6, "
                          "2% exact zeros, seed 7")
     genes["paper_phi_vse_pairs_per_s"] = PAPER_PHI_DS3526
-    samples = plain_timing(K, torch, stream, synth.samples_matrix(353, 17941, 6), reps)
+    samples = split_timing(K, torch, stream, synth.samples_matrix(353, 17941, 6), reps)
+    samples.pop("out")
     samples["workload"] = ("sample-vs-sample m=353 n=17941: per-gene level + 4 group offsets + "
                            "noise, exp, 2% exact zeros, seed 6")
     return {"gene_vs_gene": genes, "sample_vs_sample": samples}
@@ -427,6 +559,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--plain-only", action="store_true", help="time only the plain form")
+    ap.add_argument("--no-medium", action="store_true",
+                    help="skip the medium workload (4096 x 512)")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch comparison (256 matrices)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
@@ -461,7 +595,8 @@ def main() -> int:
     m, n = X.shape
     P = m * (m - 1) // 2
     Xd = torch.from_numpy(X).cuda()
-    out = K.alloc_outputs(P, m, Xd.device)
+    out_plain = K.alloc_outputs(P, m, Xd.device)
+    out = K.alloc_outputs(P, m, Xd.device)       # the batched form's
     ws = K.alloc_workspace(m, n, Xd.device)
     stream = torch.cuda.current_stream()
     scheme = K.scheme_id(args.scheme) if args.scheme is not None else K.ktau_default_scheme(n)
@@ -469,10 +604,10 @@ def main() -> int:
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        K.ktau_prepare(Xd, ws, out["n1"], stream=stream)
+        K.ktau_prepare(Xd, ws, out_plain["n1"], stream=stream)
         if ev is not None:
             ev[1].record(stream)
-        K.ktau_pairs(m, n, out, ws, scheme=scheme, q=args.q, stream=stream)
+        K.ktau_pairs(m, n, out_plain, ws, scheme=scheme, q=args.q, stream=stream)
         if ev is not None:
             ev[2].record(stream)
 
@@ -524,8 +659,11 @@ def main() -> int:
         batched = {"ms_per_step": ms_batched, "pairs_per_s": P / (ms_batched * 1e-3),
                    "step_ms_median": float(np.median(step_all)),
                    "step_ms_min": float(np.min(step_all)),
-                   "scheme": plan.plan(0)[0], "q": plan.plan(0)[1]}
+                   "scheme": plan.plan(0)[0], "q": plan.plan(0)[1],
+                   "equals_plain": outputs_equal(out, out_plain)}
         plan.close()
+    else:
+        out = out_plain
     ms_step = ms_plain if batched is None else batched["ms_per_step"]
 
     # the library's probes measure the int32 VALU and LDS peaks on this GPU
@@ -566,7 +704,10 @@ def main() -> int:
         "probes": {"valu_lane_ops_per_s": probes["valu_lane_ops_per_s"],
                    "valu_published": INT_VALU_OPS,
                    "lds_bytes_per_s": probes["lds_bytes_per_s"],
-                   "lds_reference_128B_per_clk": LDS_BYTES_PER_S},
+                   "lds_reference_128B_per_clk": LDS_BYTES_PER_S,
+                   "note": "the VALU probe issues 16 v_add_u32 per iteration (ISA); its rate "
+                           "is a denominator only where it does not exceed 256 CUs x 64 "
+                           "lanes x 2.4 GHz"},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -574,17 +715,21 @@ def main() -> int:
             "unit": "TOP/s",
             "frac": achieved / INT_VALU_OPS,
             "traffic": traffic,
-            "measured_peak": probes["valu_lane_ops_per_s"] / 1e12,
-            "frac_of_measured": achieved / probes["valu_lane_ops_per_s"],
             "kernel": kernel_tag,
             "ops_per_pair": steps_per_pair,
             "source_hash": src_hash,
         },
     }
+    if probes["valu_lane_ops_per_s"] <= INT_VALU_OPS:
+        result["roofline"]["measured_peak"] = probes["valu_lane_ops_per_s"] / 1e12
+        result["roofline"]["frac_of_measured"] = achieved / probes["valu_lane_ops_per_s"]
+    if not args.no_medium:
+        result["medium"] = medium(K, synth, torch, stream, max(5, args.steps))
     if not args.no_uneven:
         result["uneven_batch"] = uneven_batch(K, synth, torch, stream, max(2, args.steps))
     if not args.no_shapes:
         result["shapes"] = other_shapes(K, synth, torch, stream, max(2, args.steps))
+        result["large_n"] = large_n(K, synth, torch, stream, max(2, args.steps))
     if not args.no_perm:
         result["perm_test"] = perm_test(K, synth, torch, stream, 2)
     if not args.no_small:
@@ -595,7 +740,7 @@ def main() -> int:
         result["p50_ms"] = rates[-1]["p50_ms"]
         result["p99_ms"] = rates[-1]["p99_ms"]
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(X, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(X, args.cpu_seconds, gpu=out)
     print(json.dumps(result), flush=True)
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
