@@ -28,6 +28,8 @@ WsLayout ws_layout(int64_t m, int64_t n) {
   off = round_up(off + m * (int64_t)sizeof(int64_t), (int64_t)kAlign);
   L.nruns = (size_t)off;
   off = round_up(off + m * (int64_t)sizeof(int32_t), (int64_t)kAlign);
+  L.nlong = (size_t)off;
+  off = round_up(off + m * (int64_t)sizeof(int32_t), (int64_t)kAlign);
   L.runs = (size_t)off;
   off = round_up(off + m * (L.ld / 2) * (int64_t)sizeof(uint64_t), (int64_t)kAlign);
   L.heavy = (size_t)off;
@@ -55,6 +57,7 @@ MatDesc matdesc(void* ws, int64_t m, int64_t n, const ktau_pair_out& out, int sc
   d.rv.rstart = (const uint16_t*)(base + L.rstart);
   d.rv.n1 = (const int64_t*)(base + L.n1);
   d.rv.nruns = (const int32_t*)(base + L.nruns);
+  d.rv.nlong = (const int32_t*)(base + L.nlong);
   d.rv.runs = (const uint64_t*)(base + L.runs);
   d.rv.ld = L.ld;
   d.out = PairOut{out.nc, out.nd, out.n3, out.tau_b, out.tau_a};
@@ -80,7 +83,8 @@ int prepass_ws(const float* X, int64_t m, int64_t n, void* ws, int64_t* n1_out, 
   char* base = (char*)ws;
   if (launch_prepass(X, m, n, (uint16_t*)(base + L.perm), (uint16_t*)(base + L.rank),
                      (uint16_t*)(base + L.rstart), L.ld, (int64_t*)(base + L.n1), n1_out,
-                     (int32_t*)(base + L.nruns), (uint64_t*)(base + L.runs),
+                     (int32_t*)(base + L.nruns), (int32_t*)(base + L.nlong),
+                     (uint64_t*)(base + L.runs),
                      status ? status : (int32_t*)base, ws_doubled(n), (uint64_t*)(base + L.sort),
                      s) != hipSuccess)
     return KTAU_EDEVICE;
@@ -193,7 +197,8 @@ int ktau_rank(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* ra
   if (need > 0 && (!ws || ((uintptr_t)ws) % kAlign != 0)) return KTAU_EINVAL;
   if (ws_bytes < need) return KTAU_ENOMEM;
   const hipError_t e = launch_prepass(X, m, n, perm, rank, rstart, n, nullptr, n1, nullptr,
-                                      nullptr, status, false, (uint64_t*)ws, (hipStream_t)stream);
+                                      nullptr, nullptr, status, false, (uint64_t*)ws,
+                                      (hipStream_t)stream);
   return e == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
 }
 

@@ -246,7 +246,8 @@ int enqueue_batch(ktau_batch* b, hipStream_t s) {
     if (d.n > kLdsSortMax &&
         launch_prepass(d.X, d.m, d.n, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
                        (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
-                       (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status,
+                       (int32_t*)d.rv.nruns, (int32_t*)d.rv.nlong, (uint64_t*)d.rv.runs,
+                       (int32_t*)d.status,
                        ws_doubled(d.n), d.sort_tmp, s) != hipSuccess)
       return KTAU_EDEVICE;
   for (const ClassRun& c : b->classes) {

@@ -46,6 +46,12 @@ inline size_t sort_scratch_bytes(int64_t m, int64_t n) {
   return (size_t)(m < kSortSlots ? m : kSortSlots) * (size_t)sort_slot_words(n) * sizeof(uint64_t);
 }
 
+// Tie runs longer than kLongRunMin and at most kLongRunMax samples are
+// "long": the merge schemes count the inversions and joint ties inside them
+// with a sorting network per run instead of comparing every pair in them.
+constexpr int kLongRunMin = 64;
+constexpr int kLongRunMax = 512;
+
 // Sort keys: padding slots beyond n, and the sentinel read past a run end.
 // Real keys are at most 0x7FFFFFFE (15-bit tie-run start << 16 | doubled
 // rank, with n <= 16384 on that pass), so both compare above every real key
@@ -103,8 +109,11 @@ struct RankView {
   const uint16_t* rstart;   // [rows][ld] sorted position -> first position of its tie run
   const int64_t* n1;        // [rows]
   const int32_t* nruns;     // [rows] number of tie runs of length >= 2
-  // [rows][ld/2] tie runs of length >= 2 in sorted order: bits 0-15 start,
-  // 16-31 length - 1, 32-63 number of within-run pairs of the earlier runs
+  const int32_t* nlong;     // [rows] how many of them are long (listed last)
+  // [rows][ld/2] tie runs of length >= 2 in sorted order, the long ones
+  // (kLongRunMin < length <= kLongRunMax) after the others: bits 0-15
+  // start, 16-31 length - 1, 32-63 number of within-run pairs of the runs
+  // listed before it
   const uint64_t* runs;
   int64_t ld;               // row stride in elements (runs: ld/2 per row)
 };
@@ -238,8 +247,8 @@ struct MatDesc {
 // kLdsSortMax).
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* nruns, uint64_t* runs, int32_t* status, bool doubled,
-                          uint64_t* sort_tmp, hipStream_t s);
+                          int32_t* nruns, int32_t* nlong, uint64_t* runs, int32_t* status,
+                          bool doubled, uint64_t* sort_tmp, hipStream_t s);
 
 // Rank pre-pass of every row of every matrix of a descriptor table whose n is
 // at most kLdsSortMax (max_n: the largest such n); longer matrices go
@@ -277,7 +286,7 @@ hipError_t launch_tie_passes_batch(const MatDesc* descs_dev, int64_t count, int 
 // ---- host helpers shared by the API units (ktau_api.hip)
 
 struct WsLayout {
-  size_t perm, rank, rstart, n1, nruns, runs, heavy, sort, total;
+  size_t perm, rank, rstart, n1, nruns, nlong, runs, heavy, sort, total;
   int64_t ld;
 };
 WsLayout ws_layout(int64_t m, int64_t n);

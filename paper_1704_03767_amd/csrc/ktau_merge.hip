@@ -237,17 +237,17 @@ __device__ __forceinline__ void merge_load_keys(const uint16_t* row, int k0, u16
   }
 }
 
-// The n1_u pairs of positions inside one tie run of u, split evenly into
-// 2 nthreads stretches, two walked side by side per thread; returns this
-// thread's inversions inside runs and adds its equal pairs to tie.
-__device__ __forceinline__ uint32_t merge_tie_walk(const RankView& ru_v, int64_t u, int64_t n1u,
+// The first `total` pairs of positions inside one tie run of u (in the order
+// of u's run list), split evenly into 2 nthreads stretches, two walked side
+// by side per thread; returns this thread's inversions inside runs and adds
+// its equal pairs to tie.
+__device__ __forceinline__ uint32_t merge_tie_walk(const RankView& ru_v, int64_t u, uint32_t total,
                                                    const uint16_t* row, uint32_t& tie) {
   uint32_t xin = 0;
   const int64_t ld = ru_v.ld;
   const int tid = threadIdx.x, nthreads = blockDim.x;
   const uint64_t* rl = ru_v.runs + u * (ld / 2);
   const int nr = ru_v.nruns[u];
-  const uint32_t total = (uint32_t)n1u;   // < 2^31 for n <= 65536
   const uint32_t per = (uint32_t)(((uint64_t)total + 2u * nthreads - 1u) / (2u * nthreads));
   const uint64_t p0 = (uint64_t)tid * per, p1 = (uint64_t)(tid + nthreads) * per;
   const uint32_t c0 = p0 < total ? (uint32_t)(total - p0 < per ? total - p0 : per) : 0u;
@@ -260,6 +260,53 @@ __device__ __forceinline__ uint32_t merge_tie_walk(const RankView& ru_v, int64_t
       w0.step(row, i + 1 < c0, xin, tie);
       if (i < c1) w1.step(row, i + 1 < c1, xin, tie);
     }
+  }
+  return xin;
+}
+
+// One long tie run of u (len keys 2 v' from position start of the in-order
+// row) on one wave's network of 64 K >= len keys: the strict inversions inside
+// it (desc) and, on the keys reflected (0xFFFE - key, the padding kept last),
+// its strict ascents (asc); its pairs with equal v' (joint ties) are the rest,
+// len (len - 1) / 2 - desc - asc.  Adds this lane's parts to xin and tie.
+template <int K>
+__device__ __forceinline__ void long_run_count(const uint16_t* row, int start, int len, int plane,
+                                               uint32_t& xin, uint32_t& tie) {
+  using Net = bitonic::Net<K, 64>;
+  constexpr int KV = K / 2;
+  const int e0 = Net::logical_lane(plane) * K;
+  // keys of the run (reflected or not), the padding 0xFFFE last either way
+  auto load = [&](u16x2 (&key)[KV], uint32_t flip) {
+#pragma unroll
+    for (int j = 0; j < KV; ++j) {
+      const int ex = e0 + j, ey = e0 + j + KV;
+      key[j].x = (unsigned short)(ex < len ? (uint32_t)row[start + ex] ^ flip : 0xFFFEu);
+      key[j].y = (unsigned short)(ey < len ? (uint32_t)row[start + ey] ^ flip : 0xFFFEu);
+    }
+  };
+  u16x2 key[KV];
+  load(key, 0u);
+  const uint32_t desc = Net::count(key, plane, nullptr);
+  // 0xFFFE - k = k ^ 0xFFFE for even k <= 0xFFFE
+  load(key, 0xFFFEu);
+  const uint32_t asc = Net::count(key, plane, nullptr);
+  xin += desc;
+  tie += (plane == 0 ? (uint32_t)(len * (len - 1) / 2) : 0u) - desc - asc;
+}
+
+// The long runs of u (the last nl entries of its run list), wave w taking
+// runs w, w + W, ...; returns this lane's inversions inside them and adds
+// its part of their joint ties to tie.
+__device__ __forceinline__ uint32_t merge_long_runs(const uint64_t* rl, int nl, const uint16_t* row,
+                                                    uint32_t& tie) {
+  const int wave = threadIdx.x >> 6, plane = threadIdx.x & 63, waves = blockDim.x >> 6;
+  uint32_t xin = 0;
+  for (int r = wave; r < nl; r += waves) {
+    const uint64_t e = rl[r];
+    const int start = (int)(e & 0xFFFFu), len = (int)((e >> 16) & 0xFFFFu) + 1;
+    // one network size for every long run: larger or several sizes made the
+    // kernel spill registers
+    long_run_count<8>(row, start, len, plane, xin, tie);
   }
   return xin;
 }
@@ -385,12 +432,20 @@ __device__ bool pair_merge(const RankView& ry, int64_t y, const RankView& rx, in
       __syncthreads();
       if (active) merge_store_keys<K>(row, k0, key, 0xFFFFFFFFu);
       __syncthreads();
-      if (n1u != 0) share -= merge_tie_walk(ru_v, u, n1u, row, tie);
-      if constexpr (kWide) {
-        share += merge_cross_terms<K>(row, NR, scan);
-        // the keys again from the row (not kept live across the walk)
-        if (active) merge_load_keys<K>(row, k0, key);
+      if (n1u != 0) {
+        // pairs inside u's tie runs: the long runs (listed last) by
+        // networks, the others by the walk (rows longer than kDoubledMaxN,
+        // whose plain ranks do not fit the network's keys, walk all runs)
+        const uint64_t* rl = ru_v.runs + u * (ld / 2);
+        const int nr = ru_v.nruns[u];
+        const int nl = kWide ? 0 : ru_v.nlong[u];
+        const uint32_t walked = nl > 0 ? (uint32_t)(rl[nr - nl] >> 32) : (uint32_t)n1u;
+        share -= merge_tie_walk(ru_v, u, walked, row, tie);
+        if (nl > 0) share -= merge_long_runs(rl + (nr - nl), nl, row, tie);
       }
+      if constexpr (kWide) share += merge_cross_terms<K>(row, NR, scan);
+      // the keys again from the row (not kept live across the in-run counts)
+      if (active) merge_load_keys<K>(row, k0, key);
       // every walk and scan has read the row
       __syncthreads();
     }

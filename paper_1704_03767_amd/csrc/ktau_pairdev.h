@@ -208,12 +208,14 @@ struct TieWalk {
     const uint64_t e = rl[l];
     const uint32_t start = (uint32_t)e & 0xFFFFu, len = ((uint32_t)(e >> 16) & 0xFFFFu) + 1u;
     const uint32_t qi = p - (uint32_t)(e >> 32);
-    // b(b-1)/2 <= qi < b(b+1)/2 (a float estimate, then exact integer fix-up
-    // in 64 bits: b reaches 65535 in a run of 65536 samples)
-    uint64_t b = (uint64_t)((1.0f + __fsqrt_rn(8.0f * (float)qi + 1.0f)) * 0.5f);
+    // b(b-1)/2 <= qi < b(b+1)/2 (a float estimate, then exact integer
+    // fix-up).  In 32 bits: qi < 2^31 (a run of at most 65536 samples) keeps
+    // the estimate at most 65536, whose b(b-1) still fits, and the first loop
+    // leaves b <= 65535, so b(b+1) fits too.
+    uint32_t b = (uint32_t)((1.0f + __fsqrt_rn(8.0f * (float)qi + 1.0f)) * 0.5f);
     while (b * (b - 1) / 2 > qi) --b;
     while (b * (b + 1) / 2 <= qi) ++b;
-    const uint32_t a = qi - (uint32_t)(b * (b - 1) / 2);
+    const uint32_t a = qi - b * (b - 1) / 2;
     ps = row + start;
     pe = ps + len;
     pa = ps + a;

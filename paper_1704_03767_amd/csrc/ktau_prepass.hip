@@ -150,7 +150,8 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
                              uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                              uint16_t* __restrict__ rstart, int64_t ld,
                              int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
-                             int32_t* __restrict__ nruns, uint64_t* __restrict__ runs, int dbl) {
+                             int32_t* __restrict__ nruns, int32_t* __restrict__ nlong,
+                             uint64_t* __restrict__ runs, int dbl) {
   __shared__ int s_scan[kThreads / 64];
   __shared__ unsigned long long s_n1;
   const int tid = threadIdx.x;
@@ -218,41 +219,57 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
     if (n1_out) n1_out[row] = (int64_t)s_n1;
   }
   if (!runs) return;
-  // Pass 3: tie runs of length >= 2, in sorted order.  A thread owns the runs
-  // that start in its chunk (a run still open at the chunk's end stops at
-  // next_start); block scans give their index and the number of within-run
-  // pairs of all earlier runs.
+  // Pass 3: tie runs of length >= 2, in sorted order, the long ones
+  // (kLongRunMin < length <= kLongRunMax) listed after all the others.  A
+  // thread owns the runs that start in its chunk (a run still open at the
+  // chunk's end stops at next_start); block scans give each run its index and
+  // the number of within-run pairs of all runs listed before it.
   auto run_end = [&](int k) {
     int e = k + 1;
     while (e < k0 + chunk && e < n && key_at(e) == key_at(k)) ++e;
     return e == k0 + chunk && e < n ? next_start : e;
   };
+  auto starts_run = [&](int k) {
+    return k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k);
+  };
+  auto is_long = [](int len) { return len > kLongRunMin && len <= kLongRunMax; };
   // (pair counts below n(n-1)/2 < 2^31 for n <= 65536; products in 64 bits)
   auto run_pairs = [](int len) { return (int)((int64_t)len * (len - 1) / 2); };
-  int my_runs = 0, my_pairs = 0;
+  int my_s = 0, my_l = 0, my_sp = 0, my_lp = 0;
   for (int c = 0; c < chunk; ++c) {
     const int k = k0 + c;
-    if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
+    if (starts_run(k)) {
       const int len = run_end(k) - k;
-      ++my_runs;
-      my_pairs += run_pairs(len);
+      if (is_long(len)) {
+        ++my_l;
+        my_lp += run_pairs(len);
+      } else {
+        ++my_s;
+        my_sp += run_pairs(len);
+      }
     }
   }
-  int total_runs, total_pairs;
-  int run_idx = block_excl_sum(my_runs, s_scan, total_runs);
-  int pairs = block_excl_sum(my_pairs, s_scan, total_pairs);
+  int tot_s, tot_l, tot_sp, tot_lp;
+  int idx_s = block_excl_sum(my_s, s_scan, tot_s);
+  int idx_l = tot_s + block_excl_sum(my_l, s_scan, tot_l);
+  int pr_s = block_excl_sum(my_sp, s_scan, tot_sp);
+  int pr_l = tot_sp + block_excl_sum(my_lp, s_scan, tot_lp);
   uint64_t* rrow_runs = runs + row * (ld / 2);
-  for (int c = 0; c < chunk && my_runs > 0; ++c) {
+  for (int c = 0; c < chunk && my_s + my_l > 0; ++c) {
     const int k = k0 + c;
-    if (k + 1 < n && (k == 0 || key_at(k) != key_at(k - 1)) && key_at(k + 1) == key_at(k)) {
+    if (starts_run(k)) {
       const int len = run_end(k) - k;
+      const bool lg = is_long(len);
+      int& idx = lg ? idx_l : idx_s;
+      int& pr = lg ? pr_l : pr_s;
       // entry: start (bits 0-15), length - 1 (16-31), earlier pairs (32-63)
-      rrow_runs[run_idx++] =
-          ((uint64_t)(uint32_t)pairs << 32) | ((uint64_t)(len - 1) << 16) | (uint64_t)k;
-      pairs += run_pairs(len);
+      rrow_runs[idx++] =
+          ((uint64_t)(uint32_t)pr << 32) | ((uint64_t)(len - 1) << 16) | (uint64_t)k;
+      pr += run_pairs(len);
     }
   }
-  if (tid == 0 && nruns) nruns[row] = total_runs;
+  if (tid == 0 && nruns) nruns[row] = tot_s + tot_l;
+  if (tid == 0 && nlong) nlong[row] = tot_l;
 }
 
 // Ranks row `row` of one matrix; s_keys holds npow2 <= kLdsSortMax words.
@@ -260,14 +277,16 @@ __device__ __forceinline__ void prepass_row(const float* __restrict__ X, int64_t
                             uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                             uint16_t* __restrict__ rstart, int64_t ld,
                             int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
-                            int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
+                            int32_t* __restrict__ nruns, int32_t* __restrict__ nlong,
+                            uint64_t* __restrict__ runs,
                             int32_t* __restrict__ status, uint64_t* s_keys, int dbl) {
   if (load_keys(X + row * (int64_t)n, n, 0, npow2, s_keys)) {
     if (threadIdx.x == 0) atomicExch(status, KTAU_ENAN);
     return;
   }
   bitonic_stages(s_keys, npow2, 0, 2, npow2, 1);
-  rank_outputs(s_keys, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, dbl);
+  rank_outputs(s_keys, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs,
+               dbl);
 }
 
 // A row longer than kLdsSortMax (H), sorted as npow2 = 2H or 4H words in this
@@ -280,7 +299,8 @@ __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, in
                                  uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                                  uint16_t* __restrict__ rstart, int64_t ld,
                                  int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
-                                 int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
+                                 int32_t* __restrict__ nruns, int32_t* __restrict__ nlong,
+                            uint64_t* __restrict__ runs,
                                  int32_t* __restrict__ status, uint64_t* s_keys, uint64_t* g,
                                  int dbl) {
   constexpr int H = kLdsSortMax;
@@ -319,7 +339,7 @@ __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, in
       __syncthreads();
     }
   }
-  rank_outputs(g, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, dbl);
+  rank_outputs(g, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, dbl);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -327,11 +347,12 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
                uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
                int64_t* __restrict__ n1_out, int32_t* __restrict__ nruns,
-               uint64_t* __restrict__ runs, int32_t* __restrict__ status, int dbl) {
+               int32_t* __restrict__ nlong, uint64_t* __restrict__ runs,
+               int32_t* __restrict__ status, int dbl) {
   extern __shared__ uint64_t s_keys[];
   const int64_t row = blockIdx.x;
   if (row >= m) return;
-  prepass_row(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+  prepass_row(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
               s_keys, dbl);
 }
 
@@ -341,12 +362,13 @@ __global__ void __launch_bounds__(kThreads)
 prepass_long_kernel(const float* __restrict__ X, int64_t m, int n, uint16_t* __restrict__ perm,
                     uint16_t* __restrict__ rank, uint16_t* __restrict__ rstart, int64_t ld,
                     int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
-                    int32_t* __restrict__ nruns, uint64_t* __restrict__ runs,
-                    int32_t* __restrict__ status, uint64_t* __restrict__ scratch, int dbl) {
+                    int32_t* __restrict__ nruns, int32_t* __restrict__ nlong,
+                    uint64_t* __restrict__ runs, int32_t* __restrict__ status,
+                    uint64_t* __restrict__ scratch, int dbl) {
   extern __shared__ uint64_t s_keys[];
   uint64_t* g = scratch + (int64_t)blockIdx.x * sort_slot_words(n);
   for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
-    prepass_row_long(X, row, n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+    prepass_row_long(X, row, n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
                      s_keys, g, dbl);
     __syncthreads();
   }
@@ -373,7 +395,8 @@ prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
   while (npow2 < d.n) npow2 <<= 1;
   prepass_row(d.X, row, d.n, npow2, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
               (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
-              (int32_t*)d.rv.nruns, (uint64_t*)d.rv.runs, (int32_t*)d.status, s_keys, 1);
+              (int32_t*)d.rv.nruns, (int32_t*)d.rv.nlong, (uint64_t*)d.rv.runs, (int32_t*)d.status,
+              s_keys, 1);
 }
 
 // Rows longer than 8192 samples sort 128 KB of keys in LDS, above the 64 KB
@@ -402,7 +425,8 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
 
 hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, uint16_t* rank,
                           uint16_t* rstart, int64_t ld, int64_t* n1_ws, int64_t* n1_out,
-                          int32_t* nruns, uint64_t* runs, int32_t* status, bool doubled,
+                          int32_t* nruns, int32_t* nlong, uint64_t* runs, int32_t* status,
+                          bool doubled,
                           uint64_t* sort_tmp, hipStream_t s) {
   if (n > kLdsSortMax) {
     const size_t lds = (size_t)kLdsSortMax * sizeof(uint64_t);
@@ -410,7 +434,7 @@ hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, 
     if (e != hipSuccess) return e;
     const int64_t grid = m < kSortSlots ? m : kSortSlots;
     hipLaunchKernelGGL(prepass_long_kernel, dim3((unsigned)grid), dim3(kThreads), lds, s, X, m,
-                       (int)n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+                       (int)n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
                        sort_tmp, doubled ? 1 : 0);
     return hipGetLastError();
   }
@@ -420,7 +444,7 @@ hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, 
   hipError_t e = allow_lds(prepass_kernel, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)m), dim3(kThreads), lds, s, X, m, (int)n,
-                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, runs, status,
+                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
                      doubled ? 1 : 0);
   return hipGetLastError();
 }

@@ -238,6 +238,29 @@ def test_merge_schemes_every_chunk_count(scheme, n):
     _check_full(Y, scheme=scheme)
 
 
+@pytest.mark.parametrize("n", [5000, 17941, 32768])
+def test_merge_long_tie_runs(n):
+    # tie runs around the lengths the merge scheme counts by networks
+    # (64 < length <= 512) and by the pairwise walk, in both rows of a pair
+    rng = np.random.default_rng(n)
+    rows = []
+    for lens in ((65, 100, 512, 513, 63, 2, 1000), (64, 300, 65, 7), (511, 512, 128)):
+        x = rng.standard_normal(n).astype(np.float32) * 100 + 1000
+        pos = rng.permutation(n)
+        at = 0
+        for lv, ln in enumerate(lens):
+            x[pos[at:at + ln]] = np.float32(lv)            # a tie run of length ln
+            at += ln
+        rows.append(x)
+    rows.append(np.round(rng.standard_normal(n), 1).astype(np.float32))   # many long runs
+    rows.append(rng.integers(0, 40, n).astype(np.float32))
+    rows.append(rng.standard_normal(n).astype(np.float32))
+    X = np.stack(rows)
+    for scheme in ("merge_k32", "merge_k64"):
+        if K.ktau_scheme_capacity(K.scheme_id(scheme)) >= n:
+            _check_full(X, scheme=scheme)
+
+
 @pytest.mark.parametrize("n", [6000, 16384, 17941])
 def test_large_gene_expression_tiles(n):
     # several tiles and a ragged tail of rows, rows with 2% exact zeros
