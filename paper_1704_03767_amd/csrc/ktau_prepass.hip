@@ -21,7 +21,8 @@
 namespace ktau {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;       // rows up to 4096 samples, and batches
+constexpr int kLongThreads = 1024;  // rows of 8192 samples and more
 
 // Order-preserving map float32 -> uint32 with -0.0 folded onto +0.0 (IEEE
 // equality decides ties).  NaN never reaches a comparison: it is flagged.
@@ -33,6 +34,7 @@ __device__ inline uint32_t float_key(float f, bool& nan) {
 }
 
 // Block-wide exclusive scan (sum) of one int per thread; also returns the total.
+template <int T>
 __device__ inline int block_excl_sum(int v, int* sh, int& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int incl = v;
@@ -45,7 +47,7 @@ __device__ inline int block_excl_sum(int v, int* sh, int& total) {
   __syncthreads();
   int base = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) {
+  for (int w = 0; w < T / 64; ++w) {
     int s = sh[w];
     if (w < wave) base += s;
     tot += s;
@@ -56,6 +58,7 @@ __device__ inline int block_excl_sum(int v, int* sh, int& total) {
 }
 
 // Block-wide exclusive scan (max) of one non-negative int per thread.
+template <int T>
 __device__ inline int block_excl_max(int v, int* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int incl = v;
@@ -70,7 +73,7 @@ __device__ inline int block_excl_max(int v, int* sh) {
   __syncthreads();
   int base = 0;
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w)
+  for (int w = 0; w < T / 64; ++w)
     if (w < wave) base = max(base, sh[w]);
   __syncthreads();
   return max(base, excl_in_wave);
@@ -78,6 +81,7 @@ __device__ inline int block_excl_max(int v, int* sh) {
 
 // Block-wide exclusive suffix scan (min): the minimum of v over the threads
 // after this one (INT_MAX for the last).
+template <int T>
 __device__ inline int block_excl_suffix_min(int v, int* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int incl = v;
@@ -92,7 +96,7 @@ __device__ inline int block_excl_suffix_min(int v, int* sh) {
   __syncthreads();
   int after = INT_MAX;
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w)
+  for (int w = 0; w < T / 64; ++w)
     if (w > wave) after = min(after, sh[w]);
   __syncthreads();
   return min(after, excl_in_wave);
@@ -101,10 +105,11 @@ __device__ inline int block_excl_suffix_min(int v, int* sh) {
 // Loads row x as 64-bit sort words (order-preserving key << 16 | sample; all
 // ones past n) for positions base .. base+cnt-1 into s; tells every thread of
 // the block whether a NaN was seen.
+template <int T>
 __device__ inline bool load_keys(const float* __restrict__ x, int n, int base, int cnt,
                                  uint64_t* s) {
   bool any_nan = false;
-  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+  for (int i = threadIdx.x; i < cnt; i += T) {
     const int g = base + i;
     uint64_t w = ~0ull;
     if (g < n) {
@@ -123,11 +128,12 @@ __device__ inline bool load_keys(const float* __restrict__ x, int n, int base, i
 // sizes) k_first .. k_last, the first of them from stage distance j_first
 // down, every later one complete.  A block of size k holding position g runs
 // ascending iff (g & k) == 0.  Every stage distance used must be below cnt.
+template <int T>
 __device__ inline void bitonic_stages(uint64_t* s, int cnt, int base, int k_first, int k_last,
                                       int j_first) {
   for (int k = k_first; k <= k_last; k <<= 1) {
     for (int j = (k == k_first ? j_first : k >> 1); j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < cnt; i += kThreads) {
+      for (int i = threadIdx.x; i < cnt; i += T) {
         const int p = i ^ j;
         if (p > i) {
           const uint64_t a = s[i], b = s[p];
@@ -146,19 +152,20 @@ __device__ inline void bitonic_stages(uint64_t* s, int cnt, int base, int k_firs
 // Passes over the row's npow2 ascending sort words `keys` (LDS, or global
 // scratch for long rows): perm, dense ranks, run starts and n1, then the
 // list of tie runs.
+template <int T>
 __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, int n, int npow2,
                              uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                              uint16_t* __restrict__ rstart, int64_t ld,
                              int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
                              int32_t* __restrict__ nruns, int32_t* __restrict__ nlong,
                              uint64_t* __restrict__ runs, int dbl) {
-  __shared__ int s_scan[kThreads / 64];
+  __shared__ int s_scan[T / 64];
   __shared__ unsigned long long s_n1;
   const int tid = threadIdx.x;
   if (tid == 0) s_n1 = 0;
   auto key_at = [&](int k) { return keys[k] >> 16; };
   // Each thread owns `chunk` consecutive sorted positions.
-  const int chunk = npow2 / kThreads > 0 ? npow2 / kThreads : 1;
+  const int chunk = npow2 / T > 0 ? npow2 / T : 1;
   const int k0 = tid * chunk;
   // Pass 1: count value changes (for dense ranks); the last and the first
   // run start after position 0 in the chunk.
@@ -172,11 +179,11 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
     }
   }
   int total_changes;
-  const int rank_base = block_excl_sum(changes, s_scan, total_changes);
-  const int start_base = block_excl_max(last_start, s_scan);
+  const int rank_base = block_excl_sum<T>(changes, s_scan, total_changes);
+  const int start_base = block_excl_max<T>(last_start, s_scan);
   // the first run start after this chunk (n if none): where a run still open
   // at the chunk's end stops
-  const int next_start = min(block_excl_suffix_min(first_change, s_scan), n);
+  const int next_start = min(block_excl_suffix_min<T>(first_change, s_scan), n);
   // Pass 2: write perm, rank and rstart; accumulate n1.
   uint16_t* prow = perm ? perm + row * ld : nullptr;
   uint16_t* rrow = rank ? rank + row * ld : nullptr;
@@ -203,7 +210,7 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
   }
   // Padding of rows longer than the sort width (a workspace row of fewer
   // than 64 samples is padded to 128).
-  for (int k = npow2 + tid; k < ld; k += kThreads) {
+  for (int k = npow2 + tid; k < ld; k += T) {
     if (prow) prow[k] = (uint16_t)(k << dbl);
     if (srow) srow[k] = (uint16_t)k;
   }
@@ -211,7 +218,7 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
   // every real rank (0xFFFE doubled, 0xFFFF plain), so the pair kernels
   // gather padding keys without a bounds test.
   if (rrow)
-    for (int i = n + tid; i < ld; i += kThreads) rrow[i] = (uint16_t)(dbl ? 0xFFFEu : 0xFFFFu);
+    for (int i = n + tid; i < ld; i += T) rrow[i] = (uint16_t)(dbl ? 0xFFFEu : 0xFFFFu);
   atomicAdd(&s_n1, ties);
   __syncthreads();
   if (tid == 0) {
@@ -250,10 +257,10 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
     }
   }
   int tot_s, tot_l, tot_sp, tot_lp;
-  int idx_s = block_excl_sum(my_s, s_scan, tot_s);
-  int idx_l = tot_s + block_excl_sum(my_l, s_scan, tot_l);
-  int pr_s = block_excl_sum(my_sp, s_scan, tot_sp);
-  int pr_l = tot_sp + block_excl_sum(my_lp, s_scan, tot_lp);
+  int idx_s = block_excl_sum<T>(my_s, s_scan, tot_s);
+  int idx_l = tot_s + block_excl_sum<T>(my_l, s_scan, tot_l);
+  int pr_s = block_excl_sum<T>(my_sp, s_scan, tot_sp);
+  int pr_l = tot_sp + block_excl_sum<T>(my_lp, s_scan, tot_lp);
   uint64_t* rrow_runs = runs + row * (ld / 2);
   for (int c = 0; c < chunk && my_s + my_l > 0; ++c) {
     const int k = k0 + c;
@@ -273,6 +280,7 @@ __device__ __forceinline__ void rank_outputs(const uint64_t* keys, int64_t row, 
 }
 
 // Ranks row `row` of one matrix; s_keys holds npow2 <= kLdsSortMax words.
+template <int T>
 __device__ __forceinline__ void prepass_row(const float* __restrict__ X, int64_t row, int n, int npow2,
                             uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                             uint16_t* __restrict__ rstart, int64_t ld,
@@ -280,12 +288,12 @@ __device__ __forceinline__ void prepass_row(const float* __restrict__ X, int64_t
                             int32_t* __restrict__ nruns, int32_t* __restrict__ nlong,
                             uint64_t* __restrict__ runs,
                             int32_t* __restrict__ status, uint64_t* s_keys, int dbl) {
-  if (load_keys(X + row * (int64_t)n, n, 0, npow2, s_keys)) {
+  if (load_keys<T>(X + row * (int64_t)n, n, 0, npow2, s_keys)) {
     if (threadIdx.x == 0) atomicExch(status, KTAU_ENAN);
     return;
   }
-  bitonic_stages(s_keys, npow2, 0, 2, npow2, 1);
-  rank_outputs(s_keys, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs,
+  bitonic_stages<T>(s_keys, npow2, 0, 2, npow2, 1);
+  rank_outputs<T>(s_keys, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs,
                dbl);
 }
 
@@ -295,6 +303,7 @@ __device__ __forceinline__ void prepass_row(const float* __restrict__ X, int64_t
 // slot; every later level runs its stages of distance H and more over the
 // whole slot, and its stages below H per block in LDS again.  The passes then
 // read the sorted words from the slot.
+template <int T>
 __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, int64_t row, int n,
                                  uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                                  uint16_t* __restrict__ rstart, int64_t ld,
@@ -308,17 +317,17 @@ __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, in
   int npow2 = 2 * H;
   while (npow2 < n) npow2 <<= 1;
   for (int b = 0; b < npow2 / H; ++b) {
-    if (load_keys(x, n, b * H, H, s_keys)) {
+    if (load_keys<T>(x, n, b * H, H, s_keys)) {
       if (threadIdx.x == 0) atomicExch(status, KTAU_ENAN);
       return;
     }
-    bitonic_stages(s_keys, H, b * H, 2, H, 1);
-    for (int i = threadIdx.x; i < H; i += kThreads) g[b * H + i] = s_keys[i];
+    bitonic_stages<T>(s_keys, H, b * H, 2, H, 1);
+    for (int i = threadIdx.x; i < H; i += T) g[b * H + i] = s_keys[i];
     __syncthreads();
   }
   for (int k = 2 * H; k <= npow2; k <<= 1) {
     for (int j = k >> 1; j >= H; j >>= 1) {
-      for (int i = threadIdx.x; i < npow2; i += kThreads) {
+      for (int i = threadIdx.x; i < npow2; i += T) {
         const int p = i ^ j;
         if (p > i) {
           const uint64_t a = g[i], c = g[p];
@@ -332,17 +341,18 @@ __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, in
       __syncthreads();
     }
     for (int b = 0; b < npow2 / H; ++b) {
-      for (int i = threadIdx.x; i < H; i += kThreads) s_keys[i] = g[b * H + i];
+      for (int i = threadIdx.x; i < H; i += T) s_keys[i] = g[b * H + i];
       __syncthreads();
-      bitonic_stages(s_keys, H, b * H, k, k, H >> 1);
-      for (int i = threadIdx.x; i < H; i += kThreads) g[b * H + i] = s_keys[i];
+      bitonic_stages<T>(s_keys, H, b * H, k, k, H >> 1);
+      for (int i = threadIdx.x; i < H; i += T) g[b * H + i] = s_keys[i];
       __syncthreads();
     }
   }
-  rank_outputs(g, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, dbl);
+  rank_outputs<T>(g, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, dbl);
 }
 
-__global__ void __launch_bounds__(kThreads)
+template <int T>
+__global__ void __launch_bounds__(T)
 prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
                uint16_t* __restrict__ perm, uint16_t* __restrict__ rank,
                uint16_t* __restrict__ rstart, int64_t ld, int64_t* __restrict__ n1_ws,
@@ -352,13 +362,13 @@ prepass_kernel(const float* __restrict__ X, int64_t m, int n, int npow2,
   extern __shared__ uint64_t s_keys[];
   const int64_t row = blockIdx.x;
   if (row >= m) return;
-  prepass_row(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
-              s_keys, dbl);
+  prepass_row<T>(X, row, n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs,
+                 status, s_keys, dbl);
 }
 
 // Long rows: a grid of at most kSortSlots workgroups, each with its own
 // scratch slot of sort_slot_words(n) words, strides over the rows.
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kLongThreads)
 prepass_long_kernel(const float* __restrict__ X, int64_t m, int n, uint16_t* __restrict__ perm,
                     uint16_t* __restrict__ rank, uint16_t* __restrict__ rstart, int64_t ld,
                     int64_t* __restrict__ n1_ws, int64_t* __restrict__ n1_out,
@@ -368,8 +378,8 @@ prepass_long_kernel(const float* __restrict__ X, int64_t m, int n, uint16_t* __r
   extern __shared__ uint64_t s_keys[];
   uint64_t* g = scratch + (int64_t)blockIdx.x * sort_slot_words(n);
   for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
-    prepass_row_long(X, row, n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
-                     s_keys, g, dbl);
+    prepass_row_long<kLongThreads>(X, row, n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong,
+                                   runs, status, s_keys, g, dbl);
     __syncthreads();
   }
 }
@@ -393,7 +403,7 @@ prepass_batch_kernel(const MatDesc* __restrict__ descs, int64_t count,
   const int64_t row = g - row_prefix[lo];
   int npow2 = 64;
   while (npow2 < d.n) npow2 <<= 1;
-  prepass_row(d.X, row, d.n, npow2, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
+  prepass_row<kThreads>(d.X, row, d.n, npow2, (uint16_t*)d.rv.perm, (uint16_t*)d.rv.rank,
               (uint16_t*)d.rv.rstart, d.rv.ld, (int64_t*)d.rv.n1, d.n1_out,
               (int32_t*)d.rv.nruns, (int32_t*)d.rv.nlong, (uint64_t*)d.rv.runs, (int32_t*)d.status,
               s_keys, 1);
@@ -433,7 +443,7 @@ hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, 
     hipError_t e = allow_lds(prepass_long_kernel, lds);
     if (e != hipSuccess) return e;
     const int64_t grid = m < kSortSlots ? m : kSortSlots;
-    hipLaunchKernelGGL(prepass_long_kernel, dim3((unsigned)grid), dim3(kThreads), lds, s, X, m,
+    hipLaunchKernelGGL(prepass_long_kernel, dim3((unsigned)grid), dim3(kLongThreads), lds, s, X, m,
                        (int)n, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
                        sort_tmp, doubled ? 1 : 0);
     return hipGetLastError();
@@ -441,11 +451,21 @@ hipError_t launch_prepass(const float* X, int64_t m, int64_t n, uint16_t* perm, 
   int npow2 = 64;
   while (npow2 < n) npow2 <<= 1;
   const size_t lds = (size_t)npow2 * sizeof(uint64_t);
-  hipError_t e = allow_lds(prepass_kernel, lds);
+  // a row of 8192 or more keys holds 64 KB of LDS or more, so few of its
+  // workgroups share a CU: give each the full 1024 threads
+  if (npow2 >= 8192) {
+    hipError_t e = allow_lds(prepass_kernel<kLongThreads>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prepass_kernel<kLongThreads>, dim3((unsigned)m), dim3(kLongThreads), lds,
+                       s, X, m, (int)n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns,
+                       nlong, runs, status, doubled ? 1 : 0);
+    return hipGetLastError();
+  }
+  hipError_t e = allow_lds(prepass_kernel<kThreads>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(prepass_kernel, dim3((unsigned)m), dim3(kThreads), lds, s, X, m, (int)n,
-                     npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs, status,
-                     doubled ? 1 : 0);
+  hipLaunchKernelGGL(prepass_kernel<kThreads>, dim3((unsigned)m), dim3(kThreads), lds, s, X, m,
+                     (int)n, npow2, perm, rank, rstart, ld, n1_ws, n1_out, nruns, nlong, runs,
+                     status, doubled ? 1 : 0);
   return hipGetLastError();
 }
 
