@@ -227,8 +227,10 @@ int ktau_status(void* workspace_dev, void* stream);
  * sample, the samples ranked below it and those tied with it), so a pair
  * costs an AND and a population count per 32 sample pairs; counts and tau are
  * the same, bit for bit, as the network schemes'.  Its default tile edge is
- * 16.  Not a member of the numbered schemes (ktau_scheme_count); the batched,
- * query and permutation-test calls do not take it. */
+ * 16.  Not a member of the numbered schemes (ktau_scheme_count).  Batches
+ * take it too (ktau_batch_opts.force_scheme, or the autotuner's choice for
+ * sample-count classes up to 256); the query and permutation-test calls do
+ * not. */
 #define KTAU_SCHEME_NAIVE 100
 
 int ktau_scheme_count(void);
@@ -267,7 +269,8 @@ typedef struct ktau_batch_opts {
   int32_t use_graph;      /* 1 (default): capture once in a hipGraph, replay   */
   int32_t autotune;       /* 1 (default): (scheme, q) per sample-count class by
                              measurement on this device; 0: built-in defaults   */
-  int32_t force_scheme;   /* >= 0: this scheme for every matrix (-1 default)   */
+  int32_t force_scheme;   /* >= 0: this scheme (a numbered one or
+                             KTAU_SCHEME_NAIVE) for every matrix (-1 default) */
   int32_t force_q;        /* > 0: this tile edge for every matrix (0 default)  */
   const char* tune_cache; /* autotune cache file (NULL: $KTAU_TUNE_CACHE, else
                              in-process only)                                   */

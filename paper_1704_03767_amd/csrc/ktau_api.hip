@@ -208,7 +208,9 @@ size_t ktau_allpairs_workspace_size(int64_t m, int64_t n) {
 }
 
 int ktau_scheme_count(void) { return kNumSchemes; }
-const char* ktau_scheme_name(int scheme) { return scheme_name(scheme); }
+const char* ktau_scheme_name(int scheme) {
+  return scheme == KTAU_SCHEME_NAIVE ? "invalid" : scheme_name(scheme);
+}
 int64_t ktau_scheme_capacity(int scheme) {
   return (scheme >= 0 && scheme < kNumSchemes) ? scheme_capacity(scheme) : -1;
 }

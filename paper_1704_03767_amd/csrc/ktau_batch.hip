@@ -44,6 +44,12 @@ struct Plan {
   double pairs_per_s;
 };
 
+// Largest n of a scheme: the numbered ones, and the naive bit-set count.
+int64_t plan_capacity(int s) {
+  if (s == KTAU_SCHEME_NAIVE) return kBitsMaxN;
+  return (s >= 0 && s < kNumSchemes) ? scheme_capacity(s) : -1;
+}
+
 std::mutex g_tune_mu;
 std::map<int64_t, Plan> g_tuned;   // n class -> best plan (process-wide)
 
@@ -57,9 +63,11 @@ void load_cache(const char* path) {
   int q;
   double pps;
   while (fscanf(f, "%lld %63s %d %lf", &cls, name, &q, &pps) == 4) {
-    for (int s = 0; s < kNumSchemes; ++s)
-      if (strcmp(name, scheme_name(s)) == 0 && scheme_capacity(s) >= cls && q >= 1 && q <= 64)
-        g_tuned[cls] = Plan{s, q, pps};
+    for (int s = 0; s <= kNumSchemes; ++s) {
+      const int id = s < kNumSchemes ? s : KTAU_SCHEME_NAIVE;
+      if (strcmp(name, scheme_name(id)) == 0 && plan_capacity(id) >= cls && q >= 1 && q <= 64)
+        g_tuned[cls] = Plan{id, q, pps};
+    }
   }
   fclose(f);
 }
@@ -107,6 +115,8 @@ std::vector<int> candidates(int64_t cls) {
   if (cls > 4096)
     for (int s : {(int)kMergeK32, (int)kMergeK64})
       if (scheme_capacity(s) >= cls) v.push_back(s);
+  // short rows: the naive count of every sample pair from per-row bit sets
+  if (cls <= kBitsMaxN) v.push_back(KTAU_SCHEME_NAIVE);
   return v;
 }
 
@@ -125,8 +135,10 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = KTAU_OK;
   const int64_t P = m * (m - 1) / 2;
+  const size_t bits = bits_bytes(m, n);   // 0 past kBitsMaxN
   if ((!src && hipMalloc(&X, (size_t)(m * n) * sizeof(float)) != hipSuccess) ||
-      hipMalloc(&ws, L.total) != hipSuccess || hipMalloc(&tau, (size_t)P * sizeof(double)) != hipSuccess ||
+      hipMalloc(&ws, L.total + bits) != hipSuccess ||
+      hipMalloc(&tau, (size_t)P * sizeof(double)) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     rc = KTAU_ENOMEM;
   }
@@ -137,6 +149,10 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
                          m * n);
     if (hipGetLastError() != hipSuccess || clear_words((int32_t*)ws, 2, s) != KTAU_OK ||
         prepass_ws(src ? src : X, m, n, ws, nullptr, nullptr, s) != KTAU_OK)
+      rc = KTAU_EDEVICE;
+    if (rc == KTAU_OK && bits > 0 &&
+        launch_bits_prepass(matdesc(ws, m, n, ktau_pair_out{}, 0, 1, 0, 0, nullptr),
+                            (uint32_t*)((char*)ws + L.total), s) != hipSuccess)
       rc = KTAU_EDEVICE;
   }
   if (rc == KTAU_OK) {
@@ -149,7 +165,12 @@ int tune_class(int64_t cls, const float* src, int64_t m_src, int64_t n_src, hipS
         MatDesc d = matdesc(ws, m, n, out, scheme, q, 0, P, nullptr);
         float best_ms = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
-          if (hipEventRecord(e0, s) != hipSuccess || launch_pairs_plain(d, true, s) != hipSuccess ||
+          auto launch = [&]() {
+            return scheme == KTAU_SCHEME_NAIVE
+                       ? launch_bits_pairs(d, (const uint32_t*)((char*)ws + L.total), true, s)
+                       : launch_pairs_plain(d, true, s);
+          };
+          if (hipEventRecord(e0, s) != hipSuccess || launch() != hipSuccess ||
               hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rc = KTAU_EDEVICE;
             break;
@@ -193,7 +214,7 @@ Plan plan_for(int64_t n, bool autotune, const char* cache, hipStream_t s, int* r
     it = g_tuned.find(cls);
   }
   Plan p = it->second;
-  if (scheme_capacity(p.scheme) < n) p.scheme = default_scheme(n);
+  if (plan_capacity(p.scheme) < n) p.scheme = default_scheme(n);
   return p;
 }
 
@@ -258,6 +279,16 @@ int enqueue_batch(ktau_batch* b, hipStream_t s) {
         if (launch_pairs_merge(b->host_descs[p], s) != hipSuccess) return KTAU_EDEVICE;
       continue;
     }
+    if (c.scheme == KTAU_SCHEME_NAIVE) {
+      // short rows: each matrix's bit sets from its ranks, then its pairs
+      for (int64_t p = c.first; p < c.first + c.count; ++p) {
+        const MatDesc& d = b->host_descs[p];
+        if (launch_bits_prepass(d, d.bits, s) != hipSuccess ||
+            launch_bits_pairs(d, d.bits, true, s) != hipSuccess)
+          return KTAU_EDEVICE;
+      }
+      continue;
+    }
     if (launch_pairs_persistent(c.scheme, b->descs + c.first, c.count, c.total_units, c.prefix,
                                 c.counters, b->words, s) != hipSuccess)
       return KTAU_EDEVICE;
@@ -299,10 +330,12 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
     if (rc != KTAU_OK) return rc;
     if (!mats[i].X_dev) return KTAU_EINVAL;
   }
-  if (o.force_scheme >= kNumSchemes || o.force_q < 0 || o.force_q > 64) return KTAU_EINVAL;
+  if ((o.force_scheme >= kNumSchemes && o.force_scheme != KTAU_SCHEME_NAIVE) || o.force_q < 0 ||
+      o.force_q > 64)
+    return KTAU_EINVAL;
   if (o.force_scheme >= 0)
     for (int64_t i = 0; i < count; ++i)
-      if (scheme_capacity(o.force_scheme) < mats[i].n) return KTAU_EINVAL;
+      if (plan_capacity(o.force_scheme) < mats[i].n) return KTAU_EINVAL;
   const hipStream_t s = (hipStream_t)stream;
   const char* cache = o.tune_cache ? o.tune_cache : getenv("KTAU_TUNE_CACHE");
 
@@ -361,6 +394,8 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
     const ktau_matrix& mt = mats[order[p]];
     ws_off[p] = off;
     off += ws_layout(mt.m, mt.n).total;
+    if (plans[order[p]].scheme == KTAU_SCHEME_NAIVE)
+      off = (size_t)round_up((int64_t)(off + bits_bytes(mt.m, mt.n)), (int64_t)kAlign);
   }
   if (hipMalloc((void**)&b->arena, off) != hipSuccess) {
     delete b;
@@ -387,11 +422,15 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
                           mt.m * (mt.m - 1) / 2, b->words);
       d.X = mt.X_dev;
       d.n1_out = mt.out.n1;
+      if (pl.scheme == KTAU_SCHEME_NAIVE)
+        d.bits = (uint32_t*)(b->arena + ws_off[p] + ws_layout(mt.m, mt.n).total);
       d.unit_begin = acc;
       acc += d.n_units;
       uprefix.push_back(acc);
       cr.work += (double)(mt.m * (mt.m - 1) / 2) *
-                 (double)(is_merge(pl.scheme) ? mt.n : scheme_capacity(pl.scheme));
+                 (double)(is_merge(pl.scheme) || pl.scheme == KTAU_SCHEME_NAIVE
+                              ? mt.n
+                              : scheme_capacity(pl.scheme));
       rprefix[p + 1] = rprefix[p] + mt.m;
       b->host_descs[p] = d;
       b->max_n = std::max(b->max_n, (int)mt.n);
@@ -413,9 +452,11 @@ int ktau_batch_create(const ktau_matrix* mats, int64_t count, const ktau_batch_o
   for (ClassRun& c : b->classes) {
     if (rc != KTAU_OK) break;
     const hipError_t e =
-        is_merge(c.scheme)
-            ? prepare_pairs_merge(c.scheme)
-            : launch_pairs_persistent(c.scheme, b->descs, 0, 0, nullptr, nullptr, b->words, s);
+        c.scheme == KTAU_SCHEME_NAIVE
+            ? hipSuccess
+            : is_merge(c.scheme)
+                  ? prepare_pairs_merge(c.scheme)
+                  : launch_pairs_persistent(c.scheme, b->descs, 0, 0, nullptr, nullptr, b->words, s);
     if (e != hipSuccess) rc = KTAU_EDEVICE;
   }
   if (rc != KTAU_OK) {

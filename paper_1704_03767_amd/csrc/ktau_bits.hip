@@ -20,6 +20,7 @@
 // per pair in job order; larger ones run q x q tiles.
 #include "ktau_order.h"
 #include "ktau_pairdev.h"
+#include "ktau_query.h"
 
 namespace ktau {
 
@@ -303,6 +304,71 @@ __global__ void __launch_bounds__(kBlock) bits_jobs_kernel(BitsDesc b) {
   done.flush(lane, d.out, d.n);
 }
 
+// (query row, database row) pairs i = qi m + j, one per group, for the query
+// search: u = the query row, v = the database row.
+template <int NW>
+__global__ void __launch_bounds__(kBlock) bits_query_kernel(QueryDesc qd, const uint32_t* qlt,
+                                                            const uint32_t* qeq,
+                                                            const uint32_t* dlt,
+                                                            const uint32_t* deq) {
+  constexpr int G = BitsShape<NW>::G, A = BitsShape<NW>::A;
+  constexpr int kGroups = kBlock / G;
+  if (*qd.status != 0) return;
+  const int n = qd.n;
+  const int group = threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  const int64_t jobs = qd.nq * qd.m;
+  const int64_t row_words = (int64_t)n * NW;
+  Deferred<G> done;
+  auto store = [&](int64_t slot, int64_t a, int64_t b, uint32_t d, uint32_t t) {
+    store_cross(qd, slot, a, b, d, t);
+  };
+  uint32_t gt[A][NW];
+  int64_t loaded = -1;   // query row whose sets are in gt
+  uint32_t tied = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kGroups + group; i < jobs;
+       i += (int64_t)gridDim.x * kGroups) {
+    const int64_t qi = i / qd.m, j = i - qi * qd.m;
+    if (qi != loaded) {
+      load_u<NW>(qlt + qi * row_words, qeq + qi * row_words, n, lane, gt, tied);
+      loaded = qi;
+    }
+    const uint32_t* lt_v = dlt + j * row_words;
+    uint32_t nd = 0;
+#pragma unroll
+    for (int a4 = 0; a4 < A; ++a4) {
+      const int a = lane + G * a4;
+      if (a < n) {
+        uint32_t l[NW];
+        load_set<NW>(lt_v + a * NW, l);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) nd += __builtin_popcount(gt[a4][k] & l[k]);
+      }
+    }
+    const int64_t n1q = qd.rq.n1[qi], n1d = qd.rdb.n1[j];
+    uint32_t t2 = 0;
+    if (n1q > 0 && n1d > 0) t2 = joint_ties<NW>(qeq + qi * row_words, deq + j * row_words, tied, lane);
+    const uint32_t v = group_total<G>(nd | (t2 << 16));
+    done.add(lane, i, n1q, n1d, v & 0xFFFFu, v >> 17);
+    if (done.full()) done.flush_with(lane, store);
+  }
+  done.flush_with(lane, store);
+}
+
+template <int NW>
+hipError_t launch_bits_query_t(const QueryDesc& qd, const uint32_t* qbits, const uint32_t* dbbits,
+                               hipStream_t s) {
+  constexpr int kGroups = kBlock / BitsShape<NW>::G;
+  const int64_t jobs = qd.nq * qd.m;
+  int64_t grid = (jobs + kGroups - 1) / kGroups;
+  if (grid > kMaxPairGrid) grid = kMaxPairGrid;
+  if (grid < 1) return hipSuccess;
+  const size_t qset = (size_t)qd.nq * qd.n * NW, dset = (size_t)qd.m * qd.n * NW;
+  hipLaunchKernelGGL((bits_query_kernel<NW>), dim3((unsigned)grid), dim3(kBlock), 0, s, qd,
+                     qbits, qbits + qset, dbbits, dbbits + dset);
+  return hipGetLastError();
+}
+
 template <int NW>
 hipError_t launch_bits_t(const BitsDesc& b, bool tiles, hipStream_t s) {
   int64_t grid;
@@ -353,6 +419,17 @@ hipError_t launch_bits_pairs(const MatDesc& d, const uint32_t* bits, bool tiles,
     case 2: return launch_bits_t<2>(b, tiles, s);
     case 4: return launch_bits_t<4>(b, tiles, s);
     default: return launch_bits_t<8>(b, tiles, s);
+  }
+}
+
+hipError_t launch_bits_query(const QueryDesc& qd, const uint32_t* qbits, const uint32_t* dbbits,
+                             hipStream_t s) {
+  if (qd.n > kBitsMaxN) return hipErrorInvalidValue;
+  switch (bits_words_per_set(qd.n)) {
+    case 1: return launch_bits_query_t<1>(qd, qbits, dbbits, s);
+    case 2: return launch_bits_query_t<2>(qd, qbits, dbbits, s);
+    case 4: return launch_bits_query_t<4>(qd, qbits, dbbits, s);
+    default: return launch_bits_query_t<8>(qd, qbits, dbbits, s);
   }
 }
 

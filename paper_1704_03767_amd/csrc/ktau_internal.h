@@ -188,6 +188,7 @@ inline int scheme_k(int s) {
   return k[s];
 }
 inline int64_t scheme_capacity(int s) { return (int64_t)scheme_lanes(s) * scheme_k(s); }
+// Name of a numbered scheme or of KTAU_SCHEME_NAIVE ("naive_bits").
 const char* scheme_name(int s);
 int default_scheme(int64_t n);
 // The fastest network scheme that holds n (n <= 32768): the scheme of the
@@ -230,6 +231,7 @@ struct MatDesc {
   int32_t* heavy;         // [m] list of heavy rows (written by the heavy pass)
   int32_t* heavy_count;   // device scalar
   uint64_t* sort_tmp;     // pre-pass sort scratch (rows longer than kLdsSortMax)
+  uint32_t* bits;         // bit sets of KTAU_SCHEME_NAIVE (batches; NULL otherwise)
   int64_t m;
   int32_t n;
   int32_t scheme;

@@ -211,6 +211,11 @@ __global__ void __launch_bounds__(kBlock) heavy_plain_kernel(MatDesc d) {
 __global__ void __launch_bounds__(kBlock) heavy_batch_kernel(const MatDesc* descs) {
   const MatDesc d = descs[blockIdx.x];
   if (*d.status != 0) return;
+  if (d.scheme == KTAU_SCHEME_NAIVE) {
+    // the bit-set count is exact for tied pairs too: no composite pass
+    if (threadIdx.x == 0) *d.heavy_count = 0;
+    return;
+  }
   heavy_rows(d);
 }
 
@@ -309,6 +314,7 @@ const char* scheme_name(int s) {
                                 "sub8_k32",  "sub8_k64",  "block_k32", "block_k64",
                                 "block_k128", "merge_k32", "merge_k64"};
   static_assert(sizeof(names) / sizeof(names[0]) == kNumSchemes, "one name per scheme");
+  if (s == KTAU_SCHEME_NAIVE) return "naive_bits";
   return (s >= 0 && s < kNumSchemes) ? names[s] : "invalid";
 }
 

@@ -11,6 +11,7 @@ struct DbView {
   RankView rv;
   int64_t m = 0, n = 0;
   int scheme = 0;
+  uint32_t* bits = nullptr;        // bit sets of the rows (KTAU_SCHEME_NAIVE only)
   int32_t* heavy = nullptr;        // heavy-row list of the database
   int32_t* heavy_count = nullptr;
   int32_t heavy_rows = -1;         // its length, read back once (-1: unknown)
@@ -50,8 +51,15 @@ __device__ __forceinline__ void store_cross(const QueryDesc& qd, int64_t slot, i
 
 hipError_t launch_heavy(const MatDesc& d, hipStream_t s);
 
-// Device bytes a query launch needs beyond the status header.
-size_t query_scratch_bytes(int64_t nq, int64_t m, int64_t n, int k);
+// The naive count (bit sets, ktau_bits.hip) of every (query, database row)
+// pair into qd.tau / qd.nd: qbits and dbbits hold the sets of the query rows
+// and of the database rows.
+hipError_t launch_bits_query(const QueryDesc& qd, const uint32_t* qbits, const uint32_t* dbbits,
+                             hipStream_t s);
+
+// Device bytes a query launch needs beyond the status header (naive: the
+// database uses KTAU_SCHEME_NAIVE, so the query rows need bit sets too).
+size_t query_scratch_bytes(int64_t nq, int64_t m, int64_t n, int k, bool naive);
 
 // Enqueues a full query (rank, pairs, composite, top-k, write) on s; scratch
 // holds query_scratch_bytes(nq, db.m, db.n, k) bytes (256-byte aligned);

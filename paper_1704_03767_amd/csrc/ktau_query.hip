@@ -230,6 +230,11 @@ hipError_t query_composite(const QueryDesc& qd, hipStream_t s) {
 
 }  // namespace
 
+// The pair scheme of queries against a database of n samples: the naive
+// bit-set count up to 128 samples (measured faster there, as on the plain
+// path), else the fastest network scheme.
+int query_default_scheme(int64_t n) { return n <= 128 ? KTAU_SCHEME_NAIVE : network_scheme(n); }
+
 int64_t topk_rounds_len(int64_t len, int k, int64_t* out_len) {
   // returns the number of rounds; out_len receives the longest list written
   int64_t rounds = 0, cur = len, longest = 0;
@@ -243,10 +248,11 @@ int64_t topk_rounds_len(int64_t len, int k, int64_t* out_len) {
   return rounds;
 }
 
-size_t query_scratch_bytes(int64_t nq, int64_t m, int64_t n, int k) {
+size_t query_scratch_bytes(int64_t nq, int64_t m, int64_t n, int k, bool naive) {
   int64_t longest = 0;
   topk_rounds_len(m, k, &longest);
   size_t b = ws_layout(nq, n).total;
+  if (naive) b = (size_t)round_up((int64_t)(b + bits_bytes(nq, n)), (int64_t)kAlign);
   b += (size_t)round_up(nq * m * 8, (int64_t)kAlign);            // tau
   b += (size_t)round_up(nq * m * 8, (int64_t)kAlign);            // nd
   b += 2 * (size_t)round_up(nq * longest * (int64_t)sizeof(TopItem), (int64_t)kAlign);
@@ -261,7 +267,10 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
   int64_t longest = 0;
   topk_rounds_len(m, k, &longest);
   char* base = (char*)scratch;
+  const bool naive = db.scheme == KTAU_SCHEME_NAIVE;
   size_t off = ws_layout(nq, n).total;
+  uint32_t* qbits = (uint32_t*)(base + off);
+  if (naive) off = (size_t)round_up((int64_t)(off + bits_bytes(nq, n)), (int64_t)kAlign);
   double* tau = (double*)(base + off);
   off += (size_t)round_up(nq * m * 8, (int64_t)kAlign);
   int64_t* nd = (int64_t*)(base + off);
@@ -276,7 +285,9 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
   MatDesc qdesc = matdesc(scratch, nq, n, none, db.scheme, 8, 0, 0, status);
   if (clear_words((int32_t*)scratch, 2, s) != KTAU_OK) return KTAU_EDEVICE;
   if (prepass_ws(Q, nq, n, scratch, nullptr, status, s) != KTAU_OK) return KTAU_EDEVICE;
-  const bool composite = db.heavy_rows != 0 && n <= kCompositeMaxN;
+  // (the bit sets count tied pairs exactly: no composite pass)
+  const bool composite = !naive && db.heavy_rows != 0 && n <= kCompositeMaxN;
+  if (naive && launch_bits_prepass(qdesc, qbits, s) != hipSuccess) return KTAU_EDEVICE;
   if (composite && launch_heavy(qdesc, s) != hipSuccess) return KTAU_EDEVICE;
 
   QueryDesc qd;
@@ -299,6 +310,7 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
   case S: e = query_pairs_t<K, G>(qd, s); break;
     KTAU_FOR_EACH_SCHEME(KTAU_CASE)
 #undef KTAU_CASE
+    case KTAU_SCHEME_NAIVE: e = launch_bits_query(qd, qbits, db.bits, s); break;
     default: e = hipErrorInvalidValue; break;
   }
   if (e == hipSuccess && composite) e = query_composite(qd, s);
@@ -343,14 +355,19 @@ int ktau_db_create_ex(const float* X, int64_t m, int64_t n, int scheme, void* st
   *out = nullptr;
   if (m < 1 || n < 2 || m > (int64_t)0x7fffffff) return KTAU_EINVAL;
   if (n > KTAU_MAX_N_NETWORK) return KTAU_ERANGE;
-  if (scheme >= 0 && (scheme >= kNumNetSchemes || scheme_capacity(scheme) < n)) return KTAU_EINVAL;
+  if (scheme == KTAU_SCHEME_NAIVE) {
+    if (n > kBitsMaxN) return KTAU_EINVAL;
+  } else if (scheme >= 0 && (scheme >= kNumNetSchemes || scheme_capacity(scheme) < n)) {
+    return KTAU_EINVAL;
+  }
   const hipStream_t s = (hipStream_t)stream;
   ktau_db* db = new ktau_db();
   db->v.m = m;
   db->v.n = n;
-  db->v.scheme = scheme >= 0 ? scheme : network_scheme(n);
+  db->v.scheme = scheme >= 0 ? scheme : query_default_scheme(n);
+  const bool naive = db->v.scheme == KTAU_SCHEME_NAIVE;
   const WsLayout L = ws_layout(m, n);
-  if (hipMalloc(&db->ws, L.total) != hipSuccess) {
+  if (hipMalloc(&db->ws, L.total + (naive ? bits_bytes(m, n) : 0)) != hipSuccess) {
     delete db;
     return KTAU_ENOMEM;
   }
@@ -359,10 +376,12 @@ int ktau_db_create_ex(const float* X, int64_t m, int64_t n, int scheme, void* st
   db->v.rv = d.rv;
   db->v.heavy = d.heavy;
   db->v.heavy_count = d.heavy_count;
+  if (naive) db->v.bits = (uint32_t*)((char*)db->ws + L.total);
   int rc = KTAU_OK;
   if (clear_words((int32_t*)db->ws, 2, s) != KTAU_OK ||
       prepass_ws(X, m, n, db->ws, nullptr, nullptr, s) != KTAU_OK ||
-      launch_heavy(d, s) != hipSuccess)
+      launch_heavy(d, s) != hipSuccess ||
+      (naive && launch_bits_prepass(d, db->v.bits, s) != hipSuccess))
     rc = KTAU_EDEVICE;
   if (rc == KTAU_OK) {
     rc = ktau_status(db->ws, stream);
@@ -397,7 +416,8 @@ int64_t ktau_db_samples(const ktau_db* db) { return db ? db->v.n : -1; }
 
 size_t ktau_query_workspace_size(const ktau_db* db, int64_t nq, int64_t k) {
   if (!db || nq < 0 || k < 1 || k > KTAU_MAX_K) return 0;
-  return kWsHeader + query_scratch_bytes(nq > 0 ? nq : 1, db->v.m, db->v.n, (int)k);
+  return kWsHeader + query_scratch_bytes(nq > 0 ? nq : 1, db->v.m, db->v.n, (int)k,
+                                        db->v.scheme == KTAU_SCHEME_NAIVE);
 }
 
 int ktau_query(const ktau_db* db, const float* Q, int64_t nq, int64_t k, int64_t* idx_out,

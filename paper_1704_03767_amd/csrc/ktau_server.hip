@@ -62,7 +62,7 @@ class GpuExecutor : public sched::Executor {
 
   size_t bytes_for(int64_t nq, int64_t k) const override {
     return out_bytes(nq, k) + al((size_t)(nq * db_.n) * sizeof(float)) +
-           query_scratch_bytes(nq, db_.m, db_.n, (int)k);
+           query_scratch_bytes(nq, db_.m, db_.n, (int)k, db_.scheme == KTAU_SCHEME_NAIVE);
   }
 
   int start(Launch& l) override {

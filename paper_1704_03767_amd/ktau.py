@@ -161,6 +161,13 @@ def ktau_plain_default_scheme(n: int) -> int:
     return int(lib().ktau_plain_default_scheme(int(n)))
 
 
+def scheme_name(scheme: int) -> str:
+    """Name of a scheme id (a numbered scheme or KTAU_SCHEME_NAIVE)."""
+    if int(scheme) == KTAU_SCHEME_NAIVE:
+        return NAIVE_SCHEME_NAME
+    return ktau_scheme_names()[int(scheme)]
+
+
 def scheme_id(scheme) -> int:
     if scheme is None:
         return -1
@@ -436,7 +443,7 @@ class KtauBatch:
         s, q = ctypes.c_int32(), ctypes.c_int32()
         _check(_blib().ktau_batch_plan(self._h, i, ctypes.byref(s), ctypes.byref(q)),
                "ktau_batch_plan")
-        return ktau_scheme_names()[s.value], q.value
+        return scheme_name(s.value), q.value
 
     def close(self):
         if getattr(self, "_h", None):
@@ -457,8 +464,7 @@ def ktau_autotune(ns, cache_path: str | None = None, stream=None) -> list[tuple[
     qs = (ctypes.c_int32 * len(ns))()
     _check(L.ktau_autotune(arr, len(ns), cache_path.encode() if cache_path else None,
                            _stream(stream), sch, qs), "ktau_autotune")
-    names = ktau_scheme_names()
-    return [(names[s], q) for s, q in zip(sch, qs)]
+    return [(scheme_name(s), q) for s, q in zip(sch, qs)]
 
 
 # ------------------------------------------------------------ diagnostics

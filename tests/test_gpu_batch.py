@@ -73,9 +73,9 @@ def test_batch_forced_schemes():
     dev = [torch.from_numpy(X).cuda() for X in mats]
     want = [oracle.allpairs(X, "gse") for X in mats]
     for scheme in ("block_k16", "block_k8", "wave_k64", "sub16_k64", "sub8_k16", "merge_k32",
-                   "merge_k64"):
-        small = [i for i, X in enumerate(mats) if X.shape[1] <= K.ktau_scheme_capacity(
-            K.scheme_id(scheme))]
+                   "merge_k64", K.NAIVE_SCHEME_NAME):
+        cap = 256 if scheme == K.NAIVE_SCHEME_NAME else K.ktau_scheme_capacity(K.scheme_id(scheme))
+        small = [i for i, X in enumerate(mats) if X.shape[1] <= cap]
         b = K.KtauBatch([dev[i] for i in small], force_scheme=scheme, force_q=3)
         b.run()
         assert b.status() == K.KTAU_OK
@@ -96,11 +96,41 @@ def test_batch_nan_is_reported():
     b.close()
 
 
+def test_naive_class_in_batch_and_autotuner(tmp_path):
+    # short rows: the autotuner times the naive bit-set count among the
+    # candidates of classes up to 256 samples; a batch whose small matrices
+    # take it still equals the oracle and the plain calls, graph replays too
+    plans = K.ktau_autotune([32, 64, 128], str(tmp_path / "c.txt"))
+    assert any(name == K.NAIVE_SCHEME_NAME for name, _ in plans), plans
+    rng = np.random.default_rng(48)
+    mats = [np.round(rng.standard_normal((m, n)), 1).astype(np.float32)
+            for m, n in ((40, 32), (300, 64), (90, 100), (7, 128), (2, 2), (60, 256), (33, 700))]
+    mats[1][3] = 1.0                                   # a constant row
+    dev = [torch.from_numpy(X).cuda() for X in mats]
+    for force in (K.NAIVE_SCHEME_NAME, None):
+        keep = [i for i, X in enumerate(mats) if force is None or X.shape[1] <= 256]
+        b = K.KtauBatch([dev[i] for i in keep], force_scheme=force,
+                        tune_cache=str(tmp_path / "c.txt"))
+        for _ in range(2):
+            b.run()
+            assert b.status() == K.KTAU_OK
+            for j, i in enumerate(keep):
+                got = _np(b.outs[j])
+                want = oracle.allpairs(mats[i], "gse")
+                for k in ("nc", "nd", "n3", "n1"):
+                    assert np.array_equal(got[k], want[k]), (force, i, k, b.plan(j))
+                assert np.array_equal(got["tau_b"], want["tau_b"], equal_nan=True)
+        if force is not None:
+            assert all(b.plan(j)[0] == K.NAIVE_SCHEME_NAME for j in range(len(keep)))
+        b.close()
+
+
 def test_autotune_cache_roundtrip(tmp_path):
     path = str(tmp_path / "cache.txt")
     plans = K.ktau_autotune([100, 700, 1000, 3000], path)
     for (name, q), n in zip(plans, [100, 700, 1000, 3000]):
-        assert K.ktau_scheme_capacity(K.scheme_id(name)) >= n and 1 <= q <= 64
+        cap = 256 if name == K.NAIVE_SCHEME_NAME else K.ktau_scheme_capacity(K.scheme_id(name))
+        assert cap >= n and 1 <= q <= 64
     text = open(path).read().split()
     assert len(text) >= 4 * 4
     assert K.ktau_autotune([100, 700, 1000, 3000], path) == plans

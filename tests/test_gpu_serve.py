@@ -70,6 +70,29 @@ def test_query_every_scheme():
         kdb.close()
 
 
+@pytest.mark.parametrize("n,forced", [(64, None), (100, None), (128, "naive_bits"),
+                                      (200, "naive_bits"), (256, "naive_bits")])
+def test_query_naive_bits_scheme(n, forced):
+    # short rows: the database's bit sets (the default up to 128 samples)
+    db = _db(m=700, n=n, seed=60 + n)
+    Q = _queries(db, 5, 61)
+    Q[1, : n // 3] = 0.0                                     # ties on the query side
+    Q[2] = np.round(Q[2], 1)
+    kdb = S.KtauDb(torch.from_numpy(db.X).cuda(), scheme=forced)
+    got = {a: b.cpu().numpy() for a, b in S.ktau_query(kdb, torch.from_numpy(Q).cuda(), 40).items()}
+    _check_topk(got, oracle.query_topk(db.X, Q, 40))
+    kdb.close()
+    # heavily tied rows on both sides
+    rng = np.random.default_rng(n)
+    X = rng.integers(0, 3, (300, n)).astype(np.float32)
+    X[::5] = rng.standard_normal((60, n)).astype(np.float32)
+    Qt = rng.integers(0, 2, (4, n)).astype(np.float32)
+    kdb = S.KtauDb(torch.from_numpy(X).cuda(), scheme=forced)
+    got = {a: b.cpu().numpy() for a, b in S.ktau_query(kdb, torch.from_numpy(Qt).cuda(), 50).items()}
+    _check_topk(got, oracle.query_topk(X, Qt, 50))
+    kdb.close()
+
+
 @pytest.mark.parametrize("n", [8192, 16384, 24000])
 def test_query_large_samples(n):
     db = _db(m=120, n=n, seed=58)
