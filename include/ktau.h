@@ -385,10 +385,13 @@ int ktau_query(const ktau_db* db, const float* Q_dev, int64_t nq, int64_t k,
  * Requests (1..many query rows each, a k each) are queued in arrival order by
  * ktau_server_submit and served by a worker thread inside the library.  When
  * a slot (a stream) is free, the worker forms a launch from the head of the
- * queue -- the head and the requests right behind it with the same k, up to
- * max_batch_queries rows -- and admits it only if its device memory fits in
- * what is left of the mem_budget_bytes pool; otherwise it waits until
- * running launches complete.  Launches on different slots overlap on the
+ * queue -- the head and the requests right behind it, up to
+ * max_batch_queries rows; the launch computes the largest k among them and
+ * each request keeps its own first k -- and admits it only if its device
+ * memory fits in what is left of the mem_budget_bytes pool; otherwise it
+ * waits until running launches complete.  A finished launch wakes the worker
+ * from its stream (a host function), so admission follows completion without
+ * polling.  Launches on different slots overlap on the
  * device.  Each request's results are identical whether it ran alone or
  * merged with others.  Latency = completion minus submission (queueing
  * included).  Intended for callers that cannot wait on the device: all calls

@@ -5,8 +5,10 @@
 // Policy:
 //   * requests wait in arrival order;
 //   * when a slot is free, a launch is formed from the head of the queue: the
-//     head plus the requests right behind it with the same k, up to
-//     max_batch_queries query rows in all;
+//     head plus the requests right behind it, up to max_batch_queries query
+//     rows in all; it computes the top-k for the largest k among them, and
+//     each request keeps the first k of its rows' lists (the order -- |tau|
+//     descending, then row -- makes a shorter list a prefix of a longer one);
 //   * the launch is admitted only if its device bytes can be carved from the
 //     pool (first fit); otherwise it waits until running launches free
 //     memory -- so requests that arrive while others run are admitted as
@@ -184,25 +186,28 @@ class Scheduler {
       if (free_slot < 0) break;
       auto l = std::make_unique<Launch>();
       Request* head = queue_.front();
-      l->k = head->k;
       l->fail = head->force_fail;
       size_t take = 0;
       int64_t nq = 0;
       for (size_t i = 0; i < queue_.size(); ++i) {
         Request* r = queue_[i];
-        if (i > 0 && (r->k != l->k || r->force_fail || l->fail)) break;
+        if (i > 0 && (r->force_fail || l->fail)) break;
         if (i > 0 && nq + r->nq > cfg_.max_batch_queries) break;
         nq += r->nq;
         take = i + 1;
       }
       // shrink the launch until it fits the free pool (the head alone at least)
       while (take > 0) {
-        int64_t q = 0;
-        for (size_t i = 0; i < take; ++i) q += queue_[i]->nq;
+        int64_t q = 0, k = 0;
+        for (size_t i = 0; i < take; ++i) {
+          q += queue_[i]->nq;
+          k = queue_[i]->k > k ? queue_[i]->k : k;
+        }
         size_t off = 0;
-        const size_t bytes = ex_->bytes_for(q, l->k);
+        const size_t bytes = ex_->bytes_for(q, k);
         if (pool_.alloc(bytes, &off)) {
           l->nq = q;
+          l->k = k;
           l->bytes = bytes;
           l->off = off;
           break;

@@ -7,6 +7,7 @@
 // time minus submission time, so it includes queueing.
 #include <string.h>
 
+#include <atomic>
 #include <condition_variable>
 #include <memory>
 #include <mutex>
@@ -24,10 +25,27 @@ using sched::Request;
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// How a finished launch wakes the worker: a host function enqueued on the
+// slot's stream after the result copy sets the flag and notifies the
+// worker's condition variable.  It takes no lock: a callback waiting for the
+// server's mutex could deadlock a stream synchronisation the worker makes
+// while holding it; the worker's wait has a short timeout for the rare
+// notification that arrives just before it blocks.
+struct Wake {
+  std::atomic<bool> pending{false};
+  std::condition_variable* cv = nullptr;
+};
+
+void wake_worker(void* p) {
+  Wake* w = (Wake*)p;
+  w->pending.store(true, std::memory_order_release);
+  w->cv->notify_one();
+}
+
 class GpuExecutor : public sched::Executor {
  public:
-  GpuExecutor(const DbView& db, int slots, int64_t max_q, int64_t k_max, char* pool)
-      : db_(db), max_q_(max_q), k_max_(k_max), pool_(pool), slots_(slots) {}
+  GpuExecutor(const DbView& db, int slots, int64_t max_q, int64_t k_max, char* pool, Wake* wake)
+      : db_(db), max_q_(max_q), k_max_(k_max), pool_(pool), wake_(wake), slots_(slots) {}
 
   // HIP objects; false if any could not be made.
   bool init() {
@@ -105,6 +123,7 @@ class GpuExecutor : public sched::Executor {
     if (hipMemcpyAsync(s.out, base, ob, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
       return KTAU_EDEVICE;
     if (hipEventRecord(s.done, s.stream) != hipSuccess) return KTAU_EDEVICE;
+    if (hipLaunchHostFunc(s.stream, wake_worker, wake_) != hipSuccess) return KTAU_EDEVICE;
     return KTAU_OK;
   }
 
@@ -122,12 +141,20 @@ class GpuExecutor : public sched::Executor {
     const int64_t* idx = (const int64_t*)(s.out + 256);
     const double* tau = (const double*)(s.out + 256 + al((size_t)(nq * k) * 8));
     const int64_t* nd = (const int64_t*)(s.out + 256 + 2 * al((size_t)(nq * k) * 8));
+    // each request's rows, each cut to the request's own k (the launch ran
+    // the largest k of the requests it merged)
     int64_t o = 0;
     for (Request* r : l.reqs) {
-      const size_t cnt = (size_t)(r->nq * k);
-      r->idx.assign(idx + o * k, idx + o * k + cnt);
-      r->tau.assign(tau + o * k, tau + o * k + cnt);
-      r->nd.assign(nd + o * k, nd + o * k + cnt);
+      const int64_t kr = r->k;
+      r->idx.resize((size_t)(r->nq * kr));
+      r->tau.resize((size_t)(r->nq * kr));
+      r->nd.resize((size_t)(r->nq * kr));
+      for (int64_t qi = 0; qi < r->nq; ++qi) {
+        const int64_t src = (o + qi) * k, dst = qi * kr;
+        memcpy(r->idx.data() + dst, idx + src, (size_t)kr * sizeof(int64_t));
+        memcpy(r->tau.data() + dst, tau + src, (size_t)kr * sizeof(double));
+        memcpy(r->nd.data() + dst, nd + src, (size_t)kr * sizeof(int64_t));
+      }
       o += r->nq;
     }
     return status;
@@ -144,6 +171,7 @@ class GpuExecutor : public sched::Executor {
   DbView db_;
   int64_t max_q_, k_max_;
   char* pool_;
+  Wake* wake_;
   std::vector<Slot> slots_;
 };
 
@@ -167,8 +195,10 @@ struct ktau_server {
   std::unique_ptr<sched::Scheduler> sched;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
+  Wake wake;
   std::thread worker;
   bool stop = false;
+  int64_t epoch = 0;   // counts submissions and admission changes (under mu)
   int64_t next_ticket = 1;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
 };
@@ -179,15 +209,21 @@ void worker_loop(ktau_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
+    s->wake.pending.store(false, std::memory_order_relaxed);
     const auto done = s->sched->step();
     if (!done.empty()) s->cv_done.notify_all();
     if (s->stop && s->sched->idle()) break;
-    if (s->sched->running() > 0)
-      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
-    else
+    const int64_t seen = s->epoch;
+    if (s->sched->running() > 0) {
+      // until a launch finishes (its host function) or new work arrives
+      s->cv_work.wait_for(lk, std::chrono::microseconds(250), [&] {
+        return s->stop || s->epoch != seen || s->wake.pending.load(std::memory_order_acquire);
+      });
+    } else {
       s->cv_work.wait(lk, [&] {
         return s->stop || (s->sched->queued() > 0 && !s->sched->paused());
       });
+    }
   }
 }
 
@@ -221,7 +257,9 @@ int ktau_server_create(const ktau_db* db, const ktau_server_cfg* cfg, ktau_serve
     delete s;
     return KTAU_ENOMEM;
   }
-  s->ex = std::make_unique<GpuExecutor>(db->v, c.slots, c.max_batch_queries, c.k_max, s->pool);
+  s->wake.cv = &s->cv_work;
+  s->ex = std::make_unique<GpuExecutor>(db->v, c.slots, c.max_batch_queries, c.k_max, s->pool,
+                                        &s->wake);
   if (!s->ex->init()) {
     s->ex.reset();
     (void)hipFree(s->pool);
@@ -259,6 +297,7 @@ int ktau_server_submit(ktau_server* s, const float* q, int64_t nq, int64_t k, in
   *ticket = r->ticket;
   s->sched->enqueue(r.get());
   s->reqs[r->ticket] = std::move(r);
+  ++s->epoch;
   s->cv_work.notify_one();
   return KTAU_OK;
 }
@@ -322,6 +361,7 @@ int ktau_server_pause(ktau_server* s, int paused) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->sched->set_paused(paused != 0);
+    ++s->epoch;
   }
   s->cv_work.notify_all();
   return KTAU_OK;

@@ -39,7 +39,10 @@ struct Fake : Executor {
   }
   bool finished(const Launch& l) override { return done[l.slot]; }
   int collect(Launch& l) override {
-    for (Request* r : l.reqs) r->idx.assign((size_t)(r->nq * r->k), r->ticket);
+    for (Request* r : l.reqs) {
+      r->idx.assign((size_t)(r->nq * r->k), r->ticket);
+      r->nd.assign(1, l.k);   // the k the launch ran
+    }
     return 0;
   }
 };
@@ -68,6 +71,11 @@ void* st_create(int slots, long long max_batch, long long budget, long long per_
 }
 
 void st_pause(void* p, int paused) { ((World*)p)->s->set_paused(paused != 0); }
+
+long long st_launch_k(void* p, long long t) {
+  const Request* r = ((World*)p)->reqs[(size_t)t].get();
+  return r->nd.empty() ? -1 : r->nd[0];
+}
 
 long long st_submit(void* p, long long nq, long long k, int force_fail) {
   World* w = (World*)p;

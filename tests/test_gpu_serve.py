@@ -151,6 +151,29 @@ def _serve_requests(db, Q, sizes, k, concurrent, **cfg):
     return out, stats
 
 
+def test_server_merges_different_k():
+    # requests with different k merge into one launch of the largest k; each
+    # keeps the first k of its rows (a prefix of the longer list)
+    db = _db(m=700, n=500, seed=62)
+    Q = _queries(db, 9, 63)
+    kdb = S.KtauDb(torch.from_numpy(db.X).cuda())
+    srv = S.KtauServer(kdb)
+    ks = [(Q[0:2], 10), (Q[2:5], 100), (Q[5:6], 1), (Q[6:9], 37)]
+    srv.pause(True)
+    tickets = [srv.submit(q, k) for q, k in ks]
+    srv.pause(False)
+    merged = 0
+    for t, (q, k) in zip(tickets, ks):
+        st, res, lat = srv.wait(t)
+        assert st == K.KTAU_OK
+        merged = max(merged, lat["batch_requests"])
+        assert res["idx"].shape == (q.shape[0], k)
+        _check_topk(res, oracle.query_topk(db.X, q, k))
+    assert merged == len(ks)
+    srv.close()
+    kdb.close()
+
+
 def test_server_alone_equals_mix_equals_oracle():
     db = _db(m=900, n=800, seed=56)
     sizes = [1, 5, 3, 12, 1, 7, 2, 30, 4, 1, 9, 2]
@@ -246,3 +269,28 @@ def test_query_full_size_database():
     got = {a: b.cpu().numpy() for a, b in S.ktau_query(kdb, torch.from_numpy(Q).cuda(), 100).items()}
     _check_topk(got, oracle.query_topk(db.X, Q, 100))
     kdb.close()
+
+
+@pytest.mark.slow
+def test_server_full_size_200_requests():
+    # the serving workload's database (20000 x 800): 200 seeded requests of one
+    # query row each (half near a database row), k = 100, queued together so
+    # that they merge, each against the oracle's full sort of its 20000 taus
+    db = synth.database(20000, 800, 5)
+    Q = synth.queries(db, 200, 64)
+    kdb = S.KtauDb(torch.from_numpy(db.X).cuda())
+    srv = S.KtauServer(kdb)
+    srv.pause(True)
+    tickets = [srv.submit(Q[i:i + 1], 100) for i in range(200)]
+    srv.pause(False)
+    got = {"idx": [], "tau": [], "nd": []}
+    for t in tickets:
+        st, res, _ = srv.wait(t)
+        assert st == K.KTAU_OK
+        for key in got:
+            got[key].append(res[key])
+    stats = srv.stats()
+    srv.close()
+    kdb.close()
+    assert stats["merged_requests"] > 0
+    _check_topk({k: np.concatenate(v) for k, v in got.items()}, oracle.query_topk(db.X, Q, 100))

@@ -31,7 +31,7 @@ def lib(tmp_path_factory):
         ("st_cancel", [p, ll], i), ("st_peak_running", [p], ll), ("st_destroy", [p], None),
         ("st_pool_fuzz", [ll, i, ctypes.c_uint], i), ("st_fail_start", [p, ll], None),
         ("st_overlaps", [p], i), ("st_abandoned", [p], i), ("st_inflight", [p], i),
-        ("st_pause", [p, i], None),
+        ("st_pause", [p, i], None), ("st_launch_k", [p, ll], ll),
     ]:
         f = getattr(L, name)
         f.argtypes = args
@@ -57,11 +57,15 @@ def test_merging_and_fifo(lib):
     lib.st_destroy(w)
 
 
-def test_different_k_is_not_merged(lib):
+def test_different_k_merge_at_the_largest_k(lib):
     w = lib.st_create(4, 64, 1 << 30, 1000)
     t = [lib.st_submit(w, 2, k, 0) for k in (10, 10, 20, 10)]
     lib.st_step(w)
-    assert [lib.st_batch_requests(w, x) for x in t] == [2, 2, 1, 1]
+    assert [lib.st_batch_requests(w, x) for x in t] == [4, 4, 4, 4]
+    lib.st_finish_slot(w, 0)
+    assert lib.st_step(w) == 4
+    # the launch ran k = 20; every request still gets its own k per row
+    assert [lib.st_launch_k(w, x) for x in t] == [20, 20, 20, 20]
     lib.st_destroy(w)
 
 
@@ -125,7 +129,7 @@ def test_forced_failure_runs_alone(lib):
 
 
 def test_cancel_only_while_queued(lib):
-    w = lib.st_create(1, 64, 1 << 30, 1000)
+    w = lib.st_create(1, 1, 1 << 30, 1000)     # one row per launch: b waits
     a = lib.st_submit(w, 1, 5, 0)
     b = lib.st_submit(w, 1, 7, 0)
     lib.st_step(w)
