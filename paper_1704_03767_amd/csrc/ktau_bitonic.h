@@ -255,7 +255,7 @@ struct Net {
 
   // Level L: its comparator stages, its count, and the re-tag for level L+1
   // (one AND, one dot product and one XOR per VGPR).
-  template <int L>
+  template <int L, int kEnd = LOGN>
   static __device__ __forceinline__ void levels(u16x2 (&v)[KV], int lane, int plane,
                                                 uint32_t* xbuf, uint32_t& acc_in,
                                                 uint32_t& total) {
@@ -282,7 +282,7 @@ struct Net {
       const uint32_t all = (uint32_t)K * base + (uint32_t)(K * (K - 1) / 2);
       total += (all & (0u - desc)) - raw;
     }
-    if constexpr (L + 1 < LOGN) levels<L + 1>(v, lane, plane, xbuf, acc_in, total);
+    if constexpr (L + 1 < kEnd) levels<L + 1, kEnd>(v, lane, plane, xbuf, acc_in, total);
   }
 
   // Constant part of all levels: a level with nb >= 2 blocks of 2s adds
@@ -296,6 +296,30 @@ struct Net {
       c += nb >= 2 ? (nb / 2) * s * s : s * s + s * (s - 1) / 2;
     }
     return (uint32_t)c;
+  }
+
+  // The top level's term in constant_part (one ascending block of 2s = N).
+  static constexpr uint32_t top_const() {
+    const uint64_t s = (uint64_t)N / 2;
+    return (uint32_t)(s * s + s * (s - 1) / 2);
+  }
+
+  // As count, with the top level (the merge of the two halves of N/2) run
+  // only when kTop is set.  Without it the share leaves out that level's
+  // count, and the keys end as the two sorted halves re-tagged for the top
+  // level: the first half (element lanes below G/2) ascending and untagged,
+  // i.e. exactly 2*rank.
+  template <bool kTop>
+  static __device__ __forceinline__ uint32_t count_split(u16x2 (&v)[KV], int plane,
+                                                         uint32_t* xbuf) {
+    const int lane = logical_lane(plane);
+#pragma unroll
+    for (int j = 0; j < KV; ++j) v[j] = vec(bits(v[j]) ^ tag_const<0>(lane, j));
+    uint32_t acc_in = 0, total = in_lane_const();
+    levels<0, kTop ? LOGN : LOGN - 1>(v, lane, plane, xbuf, acc_in, total);
+    total -= acc_in;
+    if (plane == 0) total += kTop ? constant_part() : constant_part() - top_const();
+    return total;
   }
 
   // v: packed keys 2*rank (padding 0xFFFE) of element lane logical_lane(plane),

@@ -305,14 +305,70 @@ __device__ __forceinline__ void gather_keys(const uint16_t* row, const uint32_t 
   }
 }
 
+// Tie groups of v up to which the top level's count is taken from global
+// ranks instead of the network's last merge.
+constexpr int kTopGroups = 2;
+
+// The last merge's count without the merge.  With A the first N/2 positions
+// of u's order and B the rest, the last merge counts the pairs (a in A, b in
+// B) with v_a > v_b.  A and B together are all of v, so with
+// minrank(a) = #{x : v_x < v_a},
+//     #{b in B : v_b < v_a} = minrank(a) - #{a' in A : v_a' < v_a},
+// and summed over A the count is
+//     sum over A of minrank(a) - C(|A|, 2) + ties(A),
+// ties(A) being the pairs of A with equal v.  The keys of A are 2d (d the
+// dense rank); for the tie groups of v (dense rank d_g, size m_g),
+// minrank(a) = d(a) + sum_g (m_g - 1) [d(a) > d_g] and
+// ties(A) = sum_g C(#{a in A : d(a) = d_g}, 2).  This returns the lane's
+// share of the first sum (0 outside A) and, in eqs, its per-group counts of
+// d(a) = d_g (16 bits per group).  gk holds 2 d_g in both halves, gm the
+// m_g - 1.
+template <int K>
+__device__ __forceinline__ uint32_t top_share(const bitonic::u16x2 (&key)[K / 2], int ngroups,
+                                              const uint32_t (&gk)[kTopGroups],
+                                              const uint32_t (&gm)[kTopGroups],
+                                              uint32_t& eqs) {
+  using bitonic::bits;
+  using bitonic::u16x2;
+  using bitonic::vec;
+  constexpr int KV = K / 2;
+  constexpr uint32_t kOnes = 0x00010001u;
+  uint32_t s2 = 0;
+#pragma unroll
+  for (int j = 0; j < KV; ++j) s2 = __builtin_amdgcn_udot2(key[j], vec(kOnes), s2, false);
+  uint32_t share = s2 >> 1;
+  eqs = 0;
+#pragma unroll
+  for (int g = 0; g < kTopGroups; ++g) {
+    if (g >= ngroups) break;
+    // f = 0, 1 or 2 for a key below, at or above 2 d_g (keys are even, so
+    // (key | 1) - 2 d_g is 1 at the group and at least 3 above it)
+    uint32_t a1 = 0, a2 = 0;
+#pragma unroll
+    for (int j = 0; j < KV; ++j) {
+      const u16x2 f = bitonic::pmin(__builtin_elementwise_sub_sat(vec(bits(key[j]) | kOnes), vec(gk[g])),
+                                    vec(0x00020002u));
+      a1 = __builtin_amdgcn_udot2(f, vec(kOnes), a1, false);   // eq + 2 gt
+      a2 = __builtin_amdgcn_udot2(f, f, a2, false);            // eq + 4 gt
+    }
+    share += gm[g] * ((a2 - a1) >> 1);
+    eqs |= (2 * a1 - a2) << (16 * g);
+  }
+  return share;
+}
+
 // n_d and n3 of one pair from its gathered keys: the direct in-run tie count
 // over u's runs (when u has ties: the LDS row is overwritten with 2 v' in u
 // order), then the network's inversion count less the inversions inside u
-// runs.  Called by every lane of the group.
+// runs.  The network's last merge is skipped when its count follows from
+// v's global ranks (v has at most kTopGroups tie groups), or when the second
+// half holds only padding (nothing to count).  Called by every lane of the
+// group; rv_v / v / n give v's row and the number of samples.
 template <int K, int G>
 __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uint16_t* row,
                                                bool in_row, int k0, const RankView& ru_v,
-                                               int64_t u, int64_t n1u, uint32_t* xbuf,
+                                               int64_t u, int64_t n1u, const RankView& rv_v,
+                                               int64_t v, int n, uint32_t* xbuf,
                                                uint32_t* red, int lane, uint32_t& nd,
                                                uint32_t& n3) {
   using Net = bitonic::Net<K, G>;
@@ -359,10 +415,51 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
       }
     }
   }
+  // the last merge: counted by the network, from global ranks, or empty
+  const bool pad_half = 2 * n <= Net::N;
+  const int ngroups = pad_half ? 0 : rv_v.nruns[v];
+  const bool closed = !pad_half && ngroups <= kTopGroups;
   // n_d = inversions - inversions inside u runs, summed in one reduction
   // (exact modulo 2^32)
-  const uint32_t share = Net::count(key, lane, xbuf) - xin;
+  uint32_t share, eqs = 0;
+  if (pad_half || closed) share = Net::template count_split<false>(key, lane, xbuf) - xin;
+  else share = Net::template count_split<true>(key, lane, xbuf) - xin;
+  if (closed) {
+    uint32_t gk[kTopGroups] = {}, gm[kTopGroups] = {};
+    if (ngroups > 0) {
+      // v's tie runs (sorted position of the start, length); the dense rank of
+      // a run is its start less the surplus m - 1 of the runs before it
+      const uint64_t* rl = rv_v.runs + v * (rv_v.ld / 2);
+      uint32_t st[kTopGroups], ln[kTopGroups];
+#pragma unroll
+      for (int g = 0; g < kTopGroups; ++g) {
+        const uint64_t e = g < ngroups ? rl[g] : 0ull;
+        st[g] = (uint32_t)e & 0xFFFFu;
+        ln[g] = ((uint32_t)(e >> 16) & 0xFFFFu) + 1u;
+      }
+      if (ngroups == 2 && st[1] < st[0]) {
+        const uint32_t ts = st[0], tl = ln[0];
+        st[0] = st[1];
+        ln[0] = ln[1];
+        st[1] = ts;
+        ln[1] = tl;
+      }
+      const uint32_t d0 = st[0], d1 = st[1] - (ln[0] - 1u);
+      gk[0] = 2u * d0 * 0x00010001u;
+      gk[1] = 2u * d1 * 0x00010001u;
+      gm[0] = ln[0] - 1u;
+      gm[1] = ln[1] - 1u;
+    }
+    const uint32_t t = top_share<K>(key, ngroups, gk, gm, eqs);
+    if (Net::logical_lane(lane) < G / 2) share += t;
+    else eqs = 0;
+  }
   nd = group_sum<G>(share, red);
+  if (closed) {
+    const uint32_t e = ngroups > 0 ? group_sum<G>(eqs, red) : 0u;
+    const uint32_t c0 = e & 0xFFFFu, c1 = e >> 16, h = (uint32_t)Net::N / 2;
+    nd += c0 * (c0 - 1u) / 2u + c1 * (c1 - 1u) / 2u - h * (h - 1u) / 2u;
+  }
   n3 = n1u != 0 ? group_sum<G>(tie, red) : 0u;
 }
 
@@ -418,7 +515,7 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
   group_sync<G>();
   u16x2 key[KV];
   gather_keys<K>(row, pw, key);
-  count_gathered<K, G>(key, row, in_row, k0, ru_v, u, n1u, xbuf, red, lane, nd, n3);
+  count_gathered<K, G>(key, row, in_row, k0, ru_v, u, n1u, rv_v, v, n, xbuf, red, lane, nd, n3);
   return true;
 }
 

@@ -144,7 +144,8 @@ __device__ __forceinline__ int64_t pair_perm(const PermDesc& d, int64_t y, int64
     u16x2 key[KV];
     gather_keys<K>(row_p, pw, key);
     uint32_t nd, n3;
-    count_gathered<K, G>(key, row_p, in_row, k0, rv, u, n1u, xbuf, red, lane, nd, n3);
+    count_gathered<K, G>(key, row_p, in_row, k0, rv, u, n1u, rv, v, d.n, xbuf, red, lane,
+                         nd, n3);
     int64_t s = base + (int64_t)n3 - 2 * (int64_t)nd;
     s = s < 0 ? -s : s;
     if (b < 0) s_obs = s;
@@ -192,7 +193,7 @@ hipError_t launch_perm(const PermDesc& d, hipStream_t s) {
     case kSub8K16: return launch_perm_t<16, 8>(d, s);
     case kSub8K32: return launch_perm_t<32, 8>(d, s);
     case kSub16K32: return launch_perm_t<32, 16>(d, s);
-    case kSub32K32: return launch_perm_t<32, 32>(d, s);
+    case kSub16K64: return launch_perm_t<64, 16>(d, s);
     case kWaveK32: return launch_perm_t<32, 64>(d, s);
     case kWaveK64: return launch_perm_t<64, 64>(d, s);
     case kBlockK32: return launch_perm_t<32, 256>(d, s);

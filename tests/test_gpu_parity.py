@@ -156,6 +156,54 @@ def test_block_schemes_on_edges(n):
             _check_full(X, scheme=scheme)
 
 
+def _planted_ties(n, seed):
+    """Rows with 0, 1, 2 or 3 tie groups at chosen dense ranks: a short group
+    (2 samples), a long one (70, listed after the short runs of its row) and
+    one longer than any listed-long run (600), at the minimum, the middle and
+    the maximum of the row; pairs of groups in both orders of rank."""
+    rng = np.random.default_rng(seed)
+    rows = []
+
+    def row(groups):
+        x = rng.permutation(n).astype(np.float32) + 1.0      # distinct values 1..n
+        idx = rng.permutation(n)
+        k = 0
+        for size, where in groups:
+            size = min(size, n - k)
+            if size < 2:
+                continue
+            val = {"min": 0.0, "mid": n / 2 + 0.5, "max": n + 1.0}[where]
+            x[idx[k:k + size]] = val
+            k += size
+        return x
+
+    rows.append(row([]))
+    for size in (2, 70, 600):
+        for where in ("min", "mid", "max"):
+            rows.append(row([(size, where)]))
+    rows.append(row([(2, "max"), (70, "min")]))    # long run first in rank, listed last
+    rows.append(row([(70, "max"), (2, "min")]))
+    rows.append(row([(600, "mid"), (70, "max")]))
+    rows.append(row([(3, "min"), (5, "mid"), (70, "max")]))   # three groups
+    z = rng.lognormal(0.0, 1.0, n).astype(np.float32)
+    z[rng.random(n) < 0.02] = 0.0                              # a run of zeros
+    rows.append(z)
+    u = np.round(rng.standard_normal(n), 1).astype(np.float32)  # u-rows with ties
+    rows.append(u)
+    return np.stack(rows)
+
+
+@pytest.mark.parametrize("n", [33, 300, 513, 800, 1000, 1024, 2000, 4096])
+def test_top_level_from_global_ranks(n):
+    """The last merge's count is taken from global ranks when v has at most
+    two tie groups (and is empty when the second half is padding): every
+    scheme whose network fits, against the oracle."""
+    X = _planted_ties(n, 40 + n)
+    for scheme in ALL_SCHEMES:
+        if K.ktau_scheme_capacity(scheme) >= n and K.scheme_name(scheme).startswith(("sub", "wave", "block")):
+            _check_full(X, scheme=scheme)
+
+
 # Samples beyond 4096 run on 256-lane blocks with 32, 64 or 128 keys per lane;
 # beyond 16384 the pre-pass merges in global scratch and every pair counts its
 # ties directly.
