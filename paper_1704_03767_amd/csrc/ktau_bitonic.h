@@ -338,5 +338,301 @@ struct Net {
   }
 };
 
+
+// Bias of the half-precision keys: the smallest normal f16 pattern.
+constexpr uint32_t kHalfKeyBias = 0x0400u;
+
+// The same count with keys held as half-precision bit patterns, for groups of
+// at most 8192 keys.  A key 2*rank + tag becomes the positive normal f16
+// pattern 0x0400 + 2*rank + tag (padding 0x7BFE), so that the packed f16
+// minimum orders keys as integers do, and flipping the sign bit reverses the
+// order.  The sign bit then carries two things:
+//   * the orientation of a descending block (in place of the complement);
+//   * a per-stage pattern: in a stage whose partner sits in another lane or
+//     in the other half of the VGPR, the upper partner is held negated, so
+//     that both partners compute min(own, -partner) -- the lower one gets the
+//     minimum, the upper one minus the maximum -- in one v_pk_minimum3_f16
+//     with the negation (and, within a VGPR, the half swap) folded into the
+//     operand modifiers.  Changing the pattern between two such stages costs
+//     one XOR per VGPR, against the two extra operations (max and select) of
+//     the plain form.
+// Register stages keep min/max pairs and need both partners' signs equal;
+// the permlane stages need them equal and positive.  After the half stage the
+// high halves stay negated, so the register stages sort them descending: from
+// that level on, a lane's high halves hold its upper K/2 elements in reverse
+// order (element K-1-j in VGPR j).  Register and lane stages pair the same
+// VGPRs under that numbering; later half stages pair VGPR j with VGPR KV-1-j,
+// and the count's position weights follow it.
+
+template <int K, int G>
+struct NetS {
+  using B = Net<K, G>;
+  static constexpr int KV = B::KV, LOGK = B::LOGK, LOGKV = B::LOGKV, LOGG = B::LOGG;
+  static constexpr int LOGN = B::LOGN, N = B::N, kXChunk = B::kXChunk, kWShift = B::kWShift;
+  static_assert(N <= 8192, "keys 0x0400 + 2*rank + tag stay below the padding key 0x7BFE");
+  static constexpr uint32_t kSign = 0x80008000u;
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+  static __device__ __forceinline__ h2 hv(uint32_t x) { return __builtin_bit_cast(h2, x); }
+  static __device__ __forceinline__ uint32_t hu(h2 x) { return __builtin_bit_cast(uint32_t, x); }
+  // IEEE minimum / maximum: one instruction each, no quieting of the inputs
+  // (every key is a finite normal number)
+  static __device__ __forceinline__ uint32_t fmn(uint32_t a, uint32_t b) {
+    return hu(__builtin_elementwise_minimum(hv(a), hv(b)));
+  }
+  static __device__ __forceinline__ uint32_t fmx(uint32_t a, uint32_t b) {
+    return hu(__builtin_elementwise_maximum(hv(a), hv(b)));
+  }
+  // min(a, -b); min(a, -(a with its halves swapped)); min(a, -(b with its
+  // halves swapped))
+  static __device__ __forceinline__ uint32_t fmn_neg(uint32_t a, uint32_t b) {
+    return hu(__builtin_elementwise_minimum(hv(a), -hv(b)));
+  }
+  static __device__ __forceinline__ uint32_t fmn_neg_swap(uint32_t a) {
+    const h2 x = hv(a);
+    return hu(__builtin_elementwise_minimum(x, -__builtin_shufflevector(x, x, 1, 0)));
+  }
+  static __device__ __forceinline__ uint32_t fmn_neg_swapped(uint32_t a, uint32_t b) {
+    const h2 y = hv(b);
+    return hu(__builtin_elementwise_minimum(hv(a), -__builtin_shufflevector(y, y, 1, 0)));
+  }
+
+  // Stage on element bit k: takes a sign pattern (the upper partner negated)
+  // or needs both partners positive (permlane stages); register stages take
+  // whatever signs their partners share.
+  static constexpr bool patterned(int k) {
+    return k == LOGKV || (k >= LOGK && (B::phys_bit(k - LOGK) < 4 || B::phys_bit(k - LOGK) > 5));
+  }
+  static constexpr bool wants_plain(int k) { return k >= LOGK && !patterned(k); }
+
+  // Sign bits of the pattern keyed on element bit b (b < 0: none), for the
+  // element lane `lane`; b is the half bit or a lane bit.
+  static __device__ __forceinline__ uint32_t pattern(int lane, int b) {
+    if (b < 0) return 0u;
+    if (b == LOGKV) return 0x80000000u;
+    return ((lane >> (b - LOGK)) & 1) ? kSign : 0u;
+  }
+
+  template <int L, int k>
+  static __device__ __forceinline__ void stage(uint32_t (&v)[KV], int lane, int plane,
+                                               uint32_t* xbuf) {
+    if constexpr (k < LOGKV) {
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        if ((j >> k) & 1) continue;
+        const int p = j | (1 << k);
+        const uint32_t a = v[j], b = v[p];
+        v[j] = fmn(a, b);
+        v[p] = fmx(a, b);
+      }
+    } else if constexpr (k == LOGKV && (L == LOGKV || KV == 1)) {
+#pragma unroll
+      for (int j = 0; j < KV; ++j) v[j] = fmn_neg_swap(v[j]);
+    } else if constexpr (k == LOGKV) {
+      // the high halves hold their elements in reverse order: VGPR j's low
+      // half meets VGPR KV-1-j's high half and the reverse
+#pragma unroll
+      for (int j = 0; j < KV / 2; ++j) {
+        const uint32_t a = v[j], b = v[KV - 1 - j];
+        v[j] = fmn_neg_swapped(a, b);
+        v[KV - 1 - j] = fmn_neg_swapped(b, a);
+      }
+    } else {
+      constexpr int lb = k - LOGK;
+      constexpr int pb = B::phys_bit(lb);
+      if constexpr (pb < 4) {
+#pragma unroll
+        for (int j = 0; j < KV; ++j) v[j] = fmn_neg(v[j], lane_xor<(1 << pb)>(v[j]));
+      } else if constexpr (pb == 4 || pb == 5) {
+        if constexpr (KV >= 2) {
+#pragma unroll
+          for (int j = 0; j < KV; j += 2) {
+            uint32_t a = v[j], b = v[j + 1];
+            if constexpr (pb == 4) {
+              auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+              a = s[0];
+              b = s[1];
+            } else {
+              auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+              a = s[0];
+              b = s[1];
+            }
+            const uint32_t mn = fmn(a, b), mx = fmx(a, b);
+            if constexpr (pb == 4) {
+              auto s = __builtin_amdgcn_permlane16_swap(mn, mx, false, false);
+              v[j] = s[0];
+              v[j + 1] = s[1];
+            } else {
+              auto s = __builtin_amdgcn_permlane32_swap(mn, mx, false, false);
+              v[j] = s[0];
+              v[j + 1] = s[1];
+            }
+          }
+        } else {
+          const bool lower = ((lane >> lb) & 1) == 0;
+          const uint32_t a = v[0];
+          uint32_t part;
+          if constexpr (pb == 4) {
+            auto s = __builtin_amdgcn_permlane16_swap(a, a, false, false);
+            part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
+          } else {
+            auto s = __builtin_amdgcn_permlane32_swap(a, a, false, false);
+            part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
+          }
+          v[0] = lower ? fmn(a, part) : fmx(a, part);
+        }
+      } else {
+#pragma unroll
+        for (int j0 = 0; j0 < KV; j0 += kXChunk) {
+#pragma unroll
+          for (int j = 0; j < kXChunk; ++j) xbuf[j * G + plane] = v[j0 + j];
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < kXChunk; ++j)
+            v[j0 + j] = fmn_neg(v[j0 + j], xbuf[j * G + (plane ^ (1 << pb))]);
+          __syncthreads();
+        }
+      }
+    }
+  }
+
+  // Stages k .. 0 of a level; `cur` is the element bit the current sign
+  // pattern is keyed on (-1: none).
+  template <int L, int k, int cur>
+  static __device__ __forceinline__ void stages_down(uint32_t (&v)[KV], int lane, int plane,
+                                                     uint32_t* xbuf) {
+    constexpr int want = patterned(k) ? k : wants_plain(k) ? -1 : cur;
+    if constexpr (want != cur) {
+      const uint32_t m = pattern(lane, cur) ^ pattern(lane, want);
+#pragma unroll
+      for (int j = 0; j < KV; ++j) v[j] ^= m;
+    }
+    stage<L, k>(v, lane, plane, xbuf);
+    if constexpr (k > 0) stages_down<L, k - 1, want>(v, lane, plane, xbuf);
+  }
+
+  // Sign bit of element (lane, j, h) at the start of level L (orientation,
+  // bit L+1, xor the pattern of the level's first stage) and at its end (the
+  // half stage of levels L >= LOGKV leaves the high halves negated).
+  template <int L>
+  static __device__ __forceinline__ uint32_t sign_start(int lane, int j, int h) {
+    const uint32_t desc = L + 1 < LOGN ? B::ebit(lane, j, h, L + 1) : 0u;
+    return desc ^ (patterned(L) ? B::ebit(lane, j, h, L) : 0u);
+  }
+  template <int L>
+  static __device__ __forceinline__ uint32_t sign_end(int lane, int j, int h) {
+    const uint32_t desc = L + 1 < LOGN ? B::ebit(lane, j, h, L + 1) : 0u;
+    return desc ^ (L >= LOGKV ? (uint32_t)h : 0u);
+  }
+  // Tag (bit 0) and sign (bit 15) of each half of VGPR j at the start of
+  // level 0, the keys carrying neither.
+  static __device__ __forceinline__ uint32_t start_const(int lane, int j) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      c |= (B::ebit(lane, j, h, 0) | (sign_start<0>(lane, j, h) << 15)) << (16 * h);
+    return c;
+  }
+  // From the end of level L to the start of L+1: with t the current tag
+  // bits, v ^ t ^ retag_const sets tag bit L+1 and flips the sign where it
+  // changes.
+  template <int L>
+  static __device__ __forceinline__ uint32_t retag_const(int lane, int j) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t flip = sign_end<L>(lane, j, h) ^ sign_start<L + 1>(lane, j, h);
+      c |= (B::ebit(lane, j, h, L + 1) | (flip << 15)) << (16 * h);
+    }
+    return c;
+  }
+
+  // Key position weights of the count (see Net): inside a lane, VGPR j's
+  // halves at ascending positions of their merged block.
+  static constexpr uint32_t in_lane_weight(int L, int j) {
+    uint32_t w = 0;
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t e = ((uint32_t)h << LOGKV) | (uint32_t)j;
+      const uint32_t m2s = (2u << L) - 1u;
+      const uint32_t pos = e & m2s;
+      const uint32_t desc = (e >> (L + 1)) & 1u;
+      w |= (desc ? m2s - pos : pos) << (16 * h);
+    }
+    return w;
+  }
+
+  template <int L, int kEnd>
+  static __device__ __forceinline__ void levels(uint32_t (&v)[KV], int lane, int plane,
+                                                uint32_t* xbuf, uint32_t& acc_in,
+                                                uint32_t& total) {
+    stages_down<L, L, patterned(L) ? L : -1>(v, lane, plane, xbuf);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < KV; ++j) {
+      const uint32_t t = v[j] & 0x00010001u;
+      if constexpr (L + 1 < LOGK) {
+        acc_in = __builtin_amdgcn_udot2(vec(t), vec(in_lane_weight(L, j)), acc_in, false);
+        asm volatile("" : "+v"(acc_in));
+      } else {
+        // the half stage left the high halves negated: descending over j
+        constexpr uint32_t kW = 1u << kWShift;
+        const uint32_t w = ((uint32_t)j + kW) | (((uint32_t)(K - 1 - j) + kW) << 16);
+        acc = __builtin_amdgcn_udot2(vec(t), vec(w), acc, false);
+        asm volatile("" : "+v"(acc));
+      }
+      if constexpr (L + 1 < LOGN) v[j] = v[j] ^ t ^ retag_const<L>(lane, j);
+    }
+    if constexpr (L + 1 >= LOGK) {
+      // the lane lies inside one block of 2s, at ascending offset base of
+      // its oriented keys; a descending block's key order is the reverse
+      constexpr uint32_t m2s = (2u << L) - 1u;
+      const uint32_t base = ((uint32_t)lane & ((1u << (L + 1 - LOGK)) - 1u)) << LOGK;
+      const uint32_t rsum = acc & ((1u << kWShift) - 1u), nraw = acc >> kWShift;
+      const uint32_t desc = (L + 1 < LOGN) ? (uint32_t)(lane >> (L + 1 - LOGK)) & 1u : 0u;
+      total -= desc ? (m2s - base) * nraw - rsum : base * nraw + rsum;
+    }
+    if constexpr (L + 1 < kEnd) levels<L + 1, kEnd>(v, lane, plane, xbuf, acc_in, total);
+  }
+
+  // Over all levels, sum over blocks of s*s + s(s-1)/2.
+  static constexpr uint32_t constant_part() {
+    uint64_t c = 0;
+    for (int L = 0; L < LOGN; ++L) {
+      const uint64_t s = 1ull << L;
+      c += ((uint64_t)N / (2 * s)) * (s * s + s * (s - 1) / 2);
+    }
+    return (uint32_t)c;
+  }
+  static constexpr uint32_t top_const() { return B::top_const(); }
+
+  // Bias of the first half's keys after the network without its top level:
+  // they are 0x0400 + 2*rank.
+  static constexpr uint32_t kKeyBias = kHalfKeyBias;
+
+  // As Net::count_split, from the same packed keys 2*rank (padding 0xFFFE).
+  template <bool kTop>
+  static __device__ __forceinline__ uint32_t count_split(u16x2 (&key)[KV], int plane,
+                                                         uint32_t* xbuf) {
+    // the lane's per-level sign and tag words are formed where they are used
+    // (an empty asm keeps them from being hoisted out of the loop of pairs
+    // and held, or spilled, across it)
+    int lane = B::logical_lane(plane);
+    asm volatile("" : "+v"(lane));
+    uint32_t v[KV];
+#pragma unroll
+    for (int j = 0; j < KV; ++j) {
+      const u16x2 k = pmin(key[j], vec(0x77FE77FEu)) + vec(0x04000400u);
+      v[j] = bits(k) ^ start_const(lane, j);
+    }
+    uint32_t acc_in = 0, total = 0;
+    levels<0, kTop ? LOGN : LOGN - 1>(v, lane, plane, xbuf, acc_in, total);
+    total -= acc_in;
+    if (plane == 0) total += kTop ? constant_part() : constant_part() - top_const();
+#pragma unroll
+    for (int j = 0; j < KV; ++j) key[j] = vec(v[j]);
+    return total;
+  }
+};
+
 }  // namespace bitonic
 }  // namespace ktau

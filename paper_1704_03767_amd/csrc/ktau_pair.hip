@@ -318,14 +318,16 @@ const char* scheme_name(int s) {
   return (s >= 0 && s < kNumSchemes) ? names[s] : "invalid";
 }
 
-// Fastest network scheme per capacity class on MI355X (measured on log-normal
-// rows with a run of zeros, over every scheme whose network fits).
+// Network scheme per capacity class on MI355X: the fastest measured on
+// log-normal rows with a run of zeros, over every scheme whose network fits,
+// except up to 512 samples, where 8-lane groups (3% faster there) split the
+// in-run tie walk of heavily tied rows over too few lanes.
 int network_scheme(int64_t n) {
   if (n <= 128) return kSub8K16;
   if (n <= 256) return kSub8K32;
   if (n <= 512) return kSub16K32;
   if (n <= 1024) return kSub16K64;
-  if (n <= 2048) return kWaveK32;
+  if (n <= 2048) return kSub32K64;
   if (n <= 4096) return kWaveK64;
   if (n <= 8192) return kBlockK32;
   if (n <= 16384) return kBlockK64;

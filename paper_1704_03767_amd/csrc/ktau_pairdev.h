@@ -5,6 +5,8 @@
 // Internal to libktau.
 #pragma once
 
+#include <type_traits>
+
 #include "ktau_bitonic.h"
 #include "ktau_internal.h"
 
@@ -321,9 +323,9 @@ constexpr int kTopGroups = 2;
 // minrank(a) = d(a) + sum_g (m_g - 1) [d(a) > d_g] and
 // ties(A) = sum_g C(#{a in A : d(a) = d_g}, 2).  This returns the lane's
 // share of the first sum (0 outside A) and, in eqs, its per-group counts of
-// d(a) = d_g (16 bits per group).  gk holds 2 d_g in both halves, gm the
-// m_g - 1.
-template <int K>
+// d(a) = d_g (16 bits per group).  The keys are kBias + 2d; gk holds
+// kBias + 2 d_g in both halves, gm the m_g - 1.
+template <int K, uint32_t kBias>
 __device__ __forceinline__ uint32_t top_share(const bitonic::u16x2 (&key)[K / 2], int ngroups,
                                               const uint32_t (&gk)[kTopGroups],
                                               const uint32_t (&gm)[kTopGroups],
@@ -336,7 +338,7 @@ __device__ __forceinline__ uint32_t top_share(const bitonic::u16x2 (&key)[K / 2]
   uint32_t s2 = 0;
 #pragma unroll
   for (int j = 0; j < KV; ++j) s2 = __builtin_amdgcn_udot2(key[j], vec(kOnes), s2, false);
-  uint32_t share = s2 >> 1;
+  uint32_t share = (s2 - (uint32_t)K * kBias) >> 1;
   eqs = 0;
 #pragma unroll
   for (int g = 0; g < kTopGroups; ++g) {
@@ -371,7 +373,12 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
                                                int64_t v, int n, uint32_t* xbuf,
                                                uint32_t* red, int lane, uint32_t& nd,
                                                uint32_t& n3) {
-  using Net = bitonic::Net<K, G>;
+  // the half-precision network for groups of up to 32 lanes (measured faster
+  // there; whole waves and blocks, whose lowest lane bits exchange by
+  // permlane swaps, keep the integer network)
+  constexpr bool kHalf = G <= 32 && K * G <= 8192;
+  using Net = std::conditional_t<kHalf, bitonic::NetS<K, G>, bitonic::Net<K, G>>;
+  constexpr uint32_t kBias = kHalf ? bitonic::kHalfKeyBias : 0u;
   constexpr int KV = K / 2;
   const int64_t ld = ru_v.ld;
   uint32_t xin = 0, tie = 0;
@@ -445,13 +452,13 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
         ln[1] = tl;
       }
       const uint32_t d0 = st[0], d1 = st[1] - (ln[0] - 1u);
-      gk[0] = 2u * d0 * 0x00010001u;
-      gk[1] = 2u * d1 * 0x00010001u;
+      gk[0] = (kBias + 2u * d0) * 0x00010001u;
+      gk[1] = (kBias + 2u * d1) * 0x00010001u;
       gm[0] = ln[0] - 1u;
       gm[1] = ln[1] - 1u;
     }
-    const uint32_t t = top_share<K>(key, ngroups, gk, gm, eqs);
-    if (Net::logical_lane(lane) < G / 2) share += t;
+    const uint32_t t = top_share<K, kBias>(key, ngroups, gk, gm, eqs);
+    if (bitonic::Net<K, G>::logical_lane(lane) < G / 2) share += t;
     else eqs = 0;
   }
   nd = group_sum<G>(share, red);
@@ -503,12 +510,16 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
     load_words<K>(ru_v.perm + u * ld + k0, pw);
   } else {
     // a lane wholly past the row: its own slots of the LDS row get the
-    // padding key and it gathers them
+    // padding key and it gathers them (k0 passes through an empty asm so
+    // that these per-lane words are formed here, not held across the loop
+    // of pairs)
+    int kp = k0;
+    asm volatile("" : "+v"(kp));
     uint32_t w[KV];
 #pragma unroll
     for (int i = 0; i < KV; ++i) {
       w[i] = 0xFFFEFFFEu;
-      pw[i] = (uint32_t)(2 * (k0 + 2 * i)) | ((uint32_t)(2 * (k0 + 2 * i + 1)) << 16);
+      pw[i] = (uint32_t)(2 * (kp + 2 * i)) | ((uint32_t)(2 * (kp + 2 * i + 1)) << 16);
     }
     store_words<K>(row + k0, w);
   }

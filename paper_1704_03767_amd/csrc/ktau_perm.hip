@@ -194,7 +194,7 @@ hipError_t launch_perm(const PermDesc& d, hipStream_t s) {
     case kSub8K32: return launch_perm_t<32, 8>(d, s);
     case kSub16K32: return launch_perm_t<32, 16>(d, s);
     case kSub16K64: return launch_perm_t<64, 16>(d, s);
-    case kWaveK32: return launch_perm_t<32, 64>(d, s);
+    case kSub32K64: return launch_perm_t<64, 32>(d, s);
     case kWaveK64: return launch_perm_t<64, 64>(d, s);
     case kBlockK32: return launch_perm_t<32, 256>(d, s);
     case kBlockK64: return launch_perm_t<64, 256>(d, s);
