@@ -312,6 +312,7 @@ struct Net {
   template <bool kTop>
   static __device__ __forceinline__ uint32_t count_split(u16x2 (&v)[KV], int plane,
                                                          uint32_t* xbuf) {
+    asm volatile("" : "+v"(plane));   // per-lane words formed here, not hoisted
     const int lane = logical_lane(plane);
 #pragma unroll
     for (int j = 0; j < KV; ++j) v[j] = vec(bits(v[j]) ^ tag_const<0>(lane, j));
@@ -616,8 +617,8 @@ struct NetS {
     // the lane's per-level sign and tag words are formed where they are used
     // (an empty asm keeps them from being hoisted out of the loop of pairs
     // and held, or spilled, across it)
-    int lane = B::logical_lane(plane);
-    asm volatile("" : "+v"(lane));
+    asm volatile("" : "+v"(plane));
+    const int lane = B::logical_lane(plane);
     uint32_t v[KV];
 #pragma unroll
     for (int j = 0; j < KV; ++j) {

@@ -491,8 +491,11 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
   const int64_t u = swap ? x : y, v = swap ? y : x;
   const int64_t n1u = swap ? n1x : n1y;
   const int64_t ld = ry.ld;
-  // this lane holds sorted positions k0 .. k0+K-1 (the network's element lane)
-  const int k0 = Net::logical_lane(lane) * K;
+  // this lane holds sorted positions k0 .. k0+K-1 (the network's element lane);
+  // k0 passes through an empty asm so that the addresses formed from it are
+  // formed for each pair, not held (or spilled) across the loop of pairs
+  int k0 = Net::logical_lane(lane) * K;
+  asm volatile("" : "+v"(k0));
   // vector loads stay inside the row (ld is a multiple of 128, so a lane is
   // either wholly inside or wholly past n)
   const bool in_row = k0 + K <= ld;
@@ -510,16 +513,12 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
     load_words<K>(ru_v.perm + u * ld + k0, pw);
   } else {
     // a lane wholly past the row: its own slots of the LDS row get the
-    // padding key and it gathers them (k0 passes through an empty asm so
-    // that these per-lane words are formed here, not held across the loop
-    // of pairs)
-    int kp = k0;
-    asm volatile("" : "+v"(kp));
+    // padding key and it gathers them
     uint32_t w[KV];
 #pragma unroll
     for (int i = 0; i < KV; ++i) {
       w[i] = 0xFFFEFFFEu;
-      pw[i] = (uint32_t)(2 * (kp + 2 * i)) | ((uint32_t)(2 * (kp + 2 * i + 1)) << 16);
+      pw[i] = (uint32_t)(2 * (k0 + 2 * i)) | ((uint32_t)(2 * (k0 + 2 * i + 1)) << 16);
     }
     store_words<K>(row + k0, w);
   }
