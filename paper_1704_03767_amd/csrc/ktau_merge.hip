@@ -344,7 +344,7 @@ __device__ __forceinline__ uint32_t merge_cross_terms(const uint16_t* row, int N
 // count.  Every thread of the workgroup calls it.
 template <int K>
 __device__ __forceinline__ uint32_t merge_count(u16x2 (&key)[K / 2], uint16_t* row, int NR,
-                                                bool active, int k0, int plane) {
+                                                bool active, int k0, int plane, bool skip_top) {
   using Net = bitonic::Net<K, 64>;
   constexpr int KV = K / 2;
   constexpr int C = 64 * K;
@@ -361,6 +361,7 @@ __device__ __forceinline__ uint32_t merge_count(u16x2 (&key)[K / 2], uint16_t* r
   __syncthreads();
   for (int s = C; s < NR; s <<= 1) {
     const bool top = 2 * s >= NR;
+    if (top && skip_top) break;
     const int l0 = k0 & ~(2 * s - 1);
     const int lenA = NR - l0 < s ? NR - l0 : s;
     const int restB = NR - l0 - s;
@@ -416,6 +417,16 @@ __device__ bool pair_merge(const RankView& ry, int64_t y, const RankView& rx, in
   const int k0 = wave * C + Net::logical_lane(plane) * K;
   uint32_t share = 0;        // inversions (mod 2^32), this lane's part
   uint32_t tie = 0;
+  // The top merge (first s_top positions against the rest) is counted from
+  // v's global ranks when v has at most kTopGroups tie groups, as for the
+  // network's last merge (top_share): the first s_top positions are all
+  // samples, s_top <= (nw - 1) C < n.  Rows of the wide form, whose two
+  // passes clamp the keys, always merge.
+  int s_top = C;
+  while (2 * s_top < NR) s_top <<= 1;
+  const int ngroups = (kWide || nw < 2) ? kTopGroups + 1 : rv_v.nruns[v];
+  const bool closed = ngroups <= kTopGroups;
+  uint32_t eqs = 0;
   for (int pass = 0; pass < (kWide ? 2 : 1); ++pass) {
     // the previous pair (or pass) has finished with the row
     __syncthreads();
@@ -427,6 +438,11 @@ __device__ bool pair_merge(const RankView& ry, int64_t y, const RankView& rx, in
     __syncthreads();
     u16x2 key[KV];
     if (active) merge_gather<K>(row, ru_v.perm + u * ld, k0, ld, !kWide, key);
+    if (closed && active && k0 < s_top) {
+      uint32_t gk[kTopGroups] = {}, gm[kTopGroups] = {};
+      top_groups(rv_v, v, ngroups, 0u, gk, gm);
+      share += top_share<K, 0u>(key, ngroups, gk, gm, eqs);
+    }
     if (pass == 0 && (kWide || n1u != 0)) {
       // v' in u order replaces the rank row
       __syncthreads();
@@ -461,9 +477,14 @@ __device__ bool pair_merge(const RankView& ry, int64_t y, const RankView& rx, in
         key[j] = r + r;
       }
     }
-    share += merge_count<K>(key, row, NR, active, k0, plane);
+    share += merge_count<K>(key, row, NR, active, k0, plane, closed);
   }
   nd = merge_block_sum(share, red);
+  if (closed) {
+    const uint32_t e = ngroups > 0 ? merge_block_sum(eqs, red) : 0u;
+    const uint32_t c0 = e & 0xFFFFu, c1 = e >> 16, h = (uint32_t)s_top;
+    nd += c0 * (c0 - 1u) / 2u + c1 * (c1 - 1u) / 2u - h * (h - 1u) / 2u;
+  }
   n3 = n1u != 0 ? merge_block_sum(tie, red) : 0u;
   return true;
 }

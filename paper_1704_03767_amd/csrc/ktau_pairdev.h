@@ -359,6 +359,36 @@ __device__ __forceinline__ uint32_t top_share(const bitonic::u16x2 (&key)[K / 2]
   return share;
 }
 
+// The tie groups of row v (at most kTopGroups of them, ngroups in all) as
+// top_share takes them: gk = kBias + 2 d_g in both halves (d_g the group's
+// dense rank: its run start less the surplus m - 1 of the runs before it),
+// gm = m_g - 1.
+__device__ __forceinline__ void top_groups(const RankView& rv_v, int64_t v, int ngroups,
+                                           uint32_t kBias, uint32_t (&gk)[kTopGroups],
+                                           uint32_t (&gm)[kTopGroups]) {
+  if (ngroups <= 0) return;
+  const uint64_t* rl = rv_v.runs + v * (rv_v.ld / 2);
+  uint32_t st[kTopGroups], ln[kTopGroups];
+#pragma unroll
+  for (int g = 0; g < kTopGroups; ++g) {
+    const uint64_t e = g < ngroups ? rl[g] : 0ull;
+    st[g] = (uint32_t)e & 0xFFFFu;
+    ln[g] = ((uint32_t)(e >> 16) & 0xFFFFu) + 1u;
+  }
+  if (ngroups == 2 && st[1] < st[0]) {
+    const uint32_t ts = st[0], tl = ln[0];
+    st[0] = st[1];
+    ln[0] = ln[1];
+    st[1] = ts;
+    ln[1] = tl;
+  }
+  const uint32_t d0 = st[0], d1 = st[1] - (ln[0] - 1u);
+  gk[0] = (kBias + 2u * d0) * 0x00010001u;
+  gk[1] = (kBias + 2u * d1) * 0x00010001u;
+  gm[0] = ln[0] - 1u;
+  gm[1] = ln[1] - 1u;
+}
+
 // n_d and n3 of one pair from its gathered keys: the direct in-run tie count
 // over u's runs (when u has ties: the LDS row is overwritten with 2 v' in u
 // order), then the network's inversion count less the inversions inside u
@@ -433,30 +463,7 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
   else share = Net::template count_split<true>(key, lane, xbuf) - xin;
   if (closed) {
     uint32_t gk[kTopGroups] = {}, gm[kTopGroups] = {};
-    if (ngroups > 0) {
-      // v's tie runs (sorted position of the start, length); the dense rank of
-      // a run is its start less the surplus m - 1 of the runs before it
-      const uint64_t* rl = rv_v.runs + v * (rv_v.ld / 2);
-      uint32_t st[kTopGroups], ln[kTopGroups];
-#pragma unroll
-      for (int g = 0; g < kTopGroups; ++g) {
-        const uint64_t e = g < ngroups ? rl[g] : 0ull;
-        st[g] = (uint32_t)e & 0xFFFFu;
-        ln[g] = ((uint32_t)(e >> 16) & 0xFFFFu) + 1u;
-      }
-      if (ngroups == 2 && st[1] < st[0]) {
-        const uint32_t ts = st[0], tl = ln[0];
-        st[0] = st[1];
-        ln[0] = ln[1];
-        st[1] = ts;
-        ln[1] = tl;
-      }
-      const uint32_t d0 = st[0], d1 = st[1] - (ln[0] - 1u);
-      gk[0] = (kBias + 2u * d0) * 0x00010001u;
-      gk[1] = (kBias + 2u * d1) * 0x00010001u;
-      gm[0] = ln[0] - 1u;
-      gm[1] = ln[1] - 1u;
-    }
+    top_groups(rv_v, v, ngroups, kBias, gk, gm);
     const uint32_t t = top_share<K, kBias>(key, ngroups, gk, gm, eqs);
     if (bitonic::Net<K, G>::logical_lane(lane) < G / 2) share += t;
     else eqs = 0;

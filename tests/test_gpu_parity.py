@@ -204,6 +204,15 @@ def test_top_level_from_global_ranks(n):
             _check_full(X, scheme=scheme)
 
 
+@pytest.mark.parametrize("n", [4097, 8192, 12289, 17941, 32768])
+def test_merge_top_level_from_global_ranks(n):
+    """The merge scheme's top merge is taken from global ranks too (rows of v
+    with at most two tie groups): planted groups at both merge schemes."""
+    X = _planted_ties(n, 70 + n)
+    for name in ("merge_k32", "merge_k64"):
+        _check_full(X, scheme=K.scheme_id(name))
+
+
 # Samples beyond 4096 run on 256-lane blocks with 32, 64 or 128 keys per lane;
 # beyond 16384 the pre-pass merges in global scratch and every pair counts its
 # ties directly.
