@@ -221,16 +221,17 @@ int ktau_status(void* workspace_dev, void* stream);
  * ------------------------------------------------------------------------- */
 
 /* The naive count of Sec. 3.1 (Algorithm 1: all n(n-1)/2 sample pairs of a
- * pair of rows compared), as a scheme of the plain entry points only
- * (ktau_pairs, ktau_allpairs_ex) for n <= 256.  The comparisons are made once
+ * pair of rows compared), as a scheme of the plain entry points (ktau_pairs,
+ * ktau_allpairs_ex) for n <= 256.  The comparisons are made once
  * per row by ktau_prepare and kept in the workspace as bit sets (for every
  * sample, the samples ranked below it and those tied with it), so a pair
  * costs an AND and a population count per 32 sample pairs; counts and tau are
  * the same, bit for bit, as the network schemes'.  Its default tile edge is
  * 16.  Not a member of the numbered schemes (ktau_scheme_count).  Batches
  * take it too (ktau_batch_opts.force_scheme, or the autotuner's choice for
- * sample-count classes up to 256); the query and permutation-test calls do
- * not. */
+ * sample-count classes up to 256), and so do queries against a database
+ * created with it (ktau_db_create_ex; the default of ktau_db_create up to 128
+ * samples); the permutation test does not. */
 #define KTAU_SCHEME_NAIVE 100
 
 int ktau_scheme_count(void);
@@ -358,9 +359,12 @@ typedef struct ktau_db ktau_db;   /* opaque: ranked database resident in HBM */
  * allocation fails. */
 int ktau_db_create(const float* X_dev, int64_t m, int64_t n, void* stream,
                    ktau_db** db_out);
-/* The same with the network scheme of the query pair kernel chosen by the
- * caller (scheme < 0: the default for n; KTAU_EINVAL if it is not a network
- * scheme holding n), for tuning and tests. */
+/* The same with the scheme of the query pair kernel chosen by the caller:
+ * scheme < 0 takes the default for n (KTAU_SCHEME_NAIVE up to 128 samples,
+ * else ktau_default_scheme(n)); a network scheme must hold n and
+ * KTAU_SCHEME_NAIVE needs n <= 256 (then the database also keeps its rows'
+ * bit sets, 8 n ceil(n/32) bytes per row rounded up); anything else is
+ * KTAU_EINVAL.  For tuning and tests. */
 int ktau_db_create_ex(const float* X_dev, int64_t m, int64_t n, int scheme, void* stream,
                       ktau_db** db_out);
 void ktau_db_destroy(ktau_db* db);
