@@ -398,6 +398,19 @@ struct NetS {
     return hu(__builtin_elementwise_minimum(hv(a), -__builtin_shufflevector(y, y, 1, 0)));
   }
 
+  // a ^ b ^ c in one v_bitop3_b32 (the compiler would fold a ^ (a & m) into
+  // an AND with a literal and spend a second instruction on c); c is a
+  // scalar operand where it is the same in every lane
+  template <bool kScalarC>
+  static __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    if constexpr (kScalarC)
+      asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    else
+      asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+  }
+
   // Stage on element bit k: takes a sign pattern (the upper partner negated)
   // or needs both partners positive (permlane stages); register stages take
   // whatever signs their partners share.
@@ -581,7 +594,8 @@ struct NetS {
         acc = __builtin_amdgcn_udot2(vec(t), vec(w), acc, false);
         asm volatile("" : "+v"(acc));
       }
-      if constexpr (L + 1 < LOGN) v[j] = v[j] ^ t ^ retag_const<L>(lane, j);
+      // the re-tag word depends on the lane once bit L+2 is a lane bit
+      if constexpr (L + 1 < LOGN) v[j] = xor3<(L + 2 < LOGK)>(v[j], t, retag_const<L>(lane, j));
     }
     if constexpr (L + 1 >= LOGK) {
       // the lane lies inside one block of 2s, at ascending offset base of
@@ -622,8 +636,9 @@ struct NetS {
     uint32_t v[KV];
 #pragma unroll
     for (int j = 0; j < KV; ++j) {
-      const u16x2 k = pmin(key[j], vec(0x77FE77FEu)) + vec(0x04000400u);
-      v[j] = bits(k) ^ start_const(lane, j);
+      // the bias and the level-0 tag and sign bits (all clear in the clamped
+      // key) in one packed add
+      v[j] = bits(pmin(key[j], vec(0x77FE77FEu)) + vec(0x04000400u | start_const(lane, j)));
     }
     uint32_t acc_in = 0, total = 0;
     levels<0, kTop ? LOGN : LOGN - 1>(v, lane, plane, xbuf, acc_in, total);
