@@ -56,6 +56,19 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (M << 10) | 0x1F);
 }
 
+// a ^ b ^ c in one v_bitop3_b32 (the compiler folds a ^ (a & m) into an AND
+// with a literal and then spends a second instruction on c); c is a scalar
+// operand where it is the same in every lane.
+template <bool kScalarC>
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  if constexpr (kScalarC)
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  else
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 template <int K, int G>
 struct Net {
   static constexpr int KV = K / 2;            // VGPRs per lane
@@ -271,7 +284,9 @@ struct Net {
         const uint32_t w = ((uint32_t)j + kW) | (((uint32_t)(j + KV) + kW) << 16);
         acc = __builtin_amdgcn_udot2(vec(t), vec(w), acc, false);
       }
-      if constexpr (L + 1 < LOGN) v[j] = vec(bits(v[j]) ^ t ^ tag_const<L + 1>(lane, j));
+      // the re-tag word depends on the lane once bit L+2 is a lane bit
+      if constexpr (L + 1 < LOGN)
+        v[j] = vec(xor3<(L + 2 < LOGK)>(bits(v[j]), t, tag_const<L + 1>(lane, j)));
     }
     if constexpr (L + 1 >= LOGK) {
       // the lane lies inside one block of 2s: its offset and orientation
@@ -396,19 +411,6 @@ struct NetS {
   static __device__ __forceinline__ uint32_t fmn_neg_swapped(uint32_t a, uint32_t b) {
     const h2 y = hv(b);
     return hu(__builtin_elementwise_minimum(hv(a), -__builtin_shufflevector(y, y, 1, 0)));
-  }
-
-  // a ^ b ^ c in one v_bitop3_b32 (the compiler would fold a ^ (a & m) into
-  // an AND with a literal and spend a second instruction on c); c is a
-  // scalar operand where it is the same in every lane
-  template <bool kScalarC>
-  static __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t r;
-    if constexpr (kScalarC)
-      asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
-    else
-      asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
   }
 
   // Stage on element bit k: takes a sign pattern (the upper partner negated)

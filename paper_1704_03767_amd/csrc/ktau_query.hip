@@ -69,8 +69,6 @@ __global__ void __launch_bounds__(kBlock) query_composite_kernel(QueryDesc qd) {
 
 // ------------------------------------------------------------------ top-k
 
-constexpr int kChunk = 4096;   // candidates sorted per workgroup
-
 struct TopItem {
   uint64_t key;   // bits(|tau|) + 1, or 0 for NaN / padding
   int32_t idx;    // database row
@@ -81,6 +79,8 @@ __device__ __forceinline__ bool before(const TopItem& a, const TopItem& b) {
   return a.key > b.key || (a.key == b.key && a.idx < b.idx);
 }
 
+// Order key of tau_B: |tau| descending is key descending (the bits of a
+// non-negative double order as integers); NaN gets 0, below every number.
 __device__ __forceinline__ uint64_t tau_key(double t) {
   if (t != t) return 0;
   return (uint64_t)__double_as_longlong(fabs(t)) + 1;
@@ -106,96 +106,137 @@ __device__ void bitonic_stages(TopItem* s, int cnt, int stride, int dir) {
   }
 }
 
-// The k2 best of `cnt` items of LDS (both powers of two, k2 <= cnt), in
-// `before` order, in s[0 .. k2): every block of k2 items is sorted, then
-// blocks are merged pairwise keeping the better half -- the better of A[i]
-// and B[k2 - 1 - i] over i is the k2 best of A and B, as a bitonic sequence
-// that log2(k2) more stages sort -- until one block is left.
-__device__ void topk_items(TopItem* s, int cnt, int k2) {
-  for (int size = 2; size <= k2; size <<= 1) bitonic_stages(s, cnt, size >> 1, size < k2 ? size : 0);
-  for (int step = k2; step < cnt; step <<= 1) {
-    // blocks at multiples of step: block b keeps the best of b and b + step
-    for (int i = threadIdx.x; i < cnt / 2; i += blockDim.x) {
-      const int b = (i / k2) * 2 * step, t = i % k2;
-      if (b + step < cnt) {
-        const TopItem a = s[b + t], c = s[b + step + k2 - 1 - t];
-        if (before(c, a)) s[b + t] = c;
+constexpr int kSelThreads = 1024;
+constexpr int kSelWaves = kSelThreads / 64;
+
+// The exact top k of one query row per workgroup (R15: |tau_B| descending,
+// then database row ascending; NaN never returned; missing results idx -1,
+// tau NaN, nd -1).  A radix select finds the k-th largest key K*, 8 bits a
+// pass from the top (a histogram of the keys under the bits decided so far,
+// then the digit where the count from the top reaches what is still needed);
+// the keys above K* all belong to the top k, and of those equal to K* the
+// first in row order fill it up (a scan in row order).  The k chosen items
+// are then sorted in LDS and written out.
+__global__ void __launch_bounds__(kSelThreads)
+topk_select_kernel(const double* __restrict__ tau, const int64_t* __restrict__ nd, int64_t m,
+                   int k, int64_t* __restrict__ idx_out, double* __restrict__ tau_out,
+                   int64_t* __restrict__ nd_out) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t wtot[kSelWaves];
+  __shared__ TopItem cand[KTAU_MAX_K];
+  __shared__ uint64_t s_prefix;
+  __shared__ uint32_t s_need, s_gt, s_count;
+  const int64_t qi = blockIdx.x;
+  const double* t = tau + qi * m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  uint64_t prefix = 0;          // the bits of K* decided so far
+  uint32_t need = (uint32_t)k;  // keys under that prefix still to take
+  uint32_t gt = 0;              // keys above the prefix's range (all taken)
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
+    __syncthreads();
+    for (int64_t j = tid; j < m; j += kSelThreads) {
+      const uint64_t key = tau_key(t[j]);
+      if (shift == 56 || (key >> (shift + 8)) == (prefix >> (shift + 8)))
+        atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // lane l holds bins 255 - 4l .. 252 - 4l; counts from the top down
+      const int d0 = 255 - 4 * lane;
+      uint32_t h[4], sum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        h[q] = hist[d0 - q];
+        sum += h[q];
+      }
+      uint32_t incl = sum;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+      }
+      const uint32_t excl = incl - sum;
+      const uint64_t hit = __ballot(excl < need && incl >= need);
+      // the lane holding the digit; if all the keys under the prefix are
+      // fewer than needed, all of them are taken (digit 0, lowest bins)
+      const int src = hit ? __ffsll((unsigned long long)hit) - 1 : 63;
+      if (lane == src) {
+        uint32_t cum = excl;
+        int digit = 0;
+        if (hit) {
+          digit = d0 - 3;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (cum + h[q] >= need) {
+              digit = d0 - q;
+              break;
+            }
+            cum += h[q];
+          }
+        } else {
+          cum = incl - h[3];
+        }
+        s_prefix = prefix | ((uint64_t)digit << shift);
+        s_need = need - cum;
+        s_gt = gt + cum;
       }
     }
     __syncthreads();
-    for (int stride = k2 >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < cnt / 2; i += blockDim.x) {
-        const int b = (i / k2) * 2 * step, t = i % k2;
-        const int j = t ^ stride;
-        if (b < cnt && j > t) {
-          const TopItem a = s[b + t], c = s[b + j];
-          if (before(c, a)) {
-            s[b + t] = c;
-            s[b + j] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
+    prefix = s_prefix;
+    need = s_need;
+    gt = s_gt;
   }
-}
-
-// One round: every query's list of `len` items (or of tau values when
-// `from_tau`) is cut, chunk by chunk, to its k best; output lists have
-// ceil(len / kChunk) * k items.
-__global__ void __launch_bounds__(256)
-topk_round_kernel(const double* __restrict__ tau, const TopItem* __restrict__ in,
-                  int64_t len, int k, TopItem* __restrict__ out, int64_t out_len) {
-  extern __shared__ TopItem s_items[];
-  const int64_t qi = blockIdx.y;
-  const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-  const int64_t cnt_real = len - c0 < kChunk ? len - c0 : kChunk;
-  int cnt = 1;
-  while (cnt < cnt_real) cnt <<= 1;
-  if (cnt < k) {
-    int c = cnt;
-    while (c < k) c <<= 1;
-    cnt = c;
-  }
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    TopItem t;
-    t.key = 0;
-    t.idx = 0x7FFFFFFF;
-    t.pad = 0;
-    if (i < cnt_real) {
-      const int64_t g = c0 + i;
-      if (tau) {
-        t.key = tau_key(tau[qi * len + g]);
-        t.idx = (int32_t)g;
-      } else {
-        t = in[qi * len + g];
-      }
-    }
-    s_items[i] = t;
-  }
+  const uint64_t kstar = prefix;
+  // keys above K*, in any order
+  if (tid == 0) s_count = 0;
   __syncthreads();
+  for (int64_t j = tid; j < m; j += kSelThreads) {
+    const uint64_t key = tau_key(t[j]);
+    if (key > kstar) {
+      const uint32_t at = atomicAdd(&s_count, 1u);
+      cand[at] = TopItem{key, (int32_t)j, 0};
+    }
+  }
+  // keys equal to K* (never NaN), the first `take` in row order
+  const uint32_t take = kstar == 0 ? 0u : need;
+  uint32_t run = 0;
+  for (int64_t j0 = 0; j0 < m && run < take; j0 += kSelThreads) {
+    const int64_t j = j0 + tid;
+    const bool eq = j < m && tau_key(t[j]) == kstar;
+    const uint64_t mask = __ballot(eq);
+    const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wtot[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t ahead = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kSelWaves; ++w) {
+      const uint32_t c = wtot[w];
+      ahead += w < wave ? c : 0u;
+      all += c;
+    }
+    const uint32_t at = run + ahead + below;
+    if (eq && at < take) cand[gt + at] = TopItem{kstar, (int32_t)j, 0};
+    run += all;
+    __syncthreads();
+  }
+  const uint32_t filled = gt + (run < take ? run : take);
   int k2 = 1;
   while (k2 < k) k2 <<= 1;
-  topk_items(s_items, cnt, k2);
-  for (int i = threadIdx.x; i < k; i += blockDim.x)
-    out[qi * out_len + (int64_t)blockIdx.x * k + i] = s_items[i];
-}
-
-// Final k items of each query -> caller arrays (idx -1, tau NaN, nd -1 for
-// missing results).
-__global__ void topk_write_kernel(const TopItem* __restrict__ items, int64_t nq, int k,
-                                  const double* __restrict__ tau, const int64_t* __restrict__ nd,
-                                  int64_t m, int64_t* __restrict__ idx_out,
-                                  double* __restrict__ tau_out, int64_t* __restrict__ nd_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nq * k) return;
-  const int64_t qi = i / k;
-  const TopItem t = items[i];
-  const bool ok = t.key != 0;
-  const int64_t j = t.idx;
-  if (idx_out) idx_out[i] = ok ? j : -1;
-  if (tau_out) tau_out[i] = ok ? tau[qi * m + j] : __builtin_nan("");
-  if (nd_out) nd_out[i] = ok ? nd[qi * m + j] : -1;
+  for (int i = tid; i < k2; i += kSelThreads)
+    if ((uint32_t)i >= filled) cand[i] = TopItem{0, 0x7FFFFFFF, 0};
+  __syncthreads();
+  for (int size = 2; size <= k2; size <<= 1)
+    bitonic_stages(cand, k2, size >> 1, size < k2 ? size : 0);
+  for (int i = tid; i < k; i += kSelThreads) {
+    const TopItem c = cand[i];
+    const bool ok = c.key != 0;
+    const int64_t o = qi * k + i;
+    if (idx_out) idx_out[o] = ok ? (int64_t)c.idx : -1;
+    if (tau_out) tau_out[o] = ok ? t[c.idx] : __builtin_nan("");
+    if (nd_out) nd_out[o] = ok ? nd[qi * m + c.idx] : -1;
+  }
 }
 
 template <int K, int G>
@@ -235,27 +276,12 @@ hipError_t query_composite(const QueryDesc& qd, hipStream_t s) {
 // path), else the fastest network scheme.
 int query_default_scheme(int64_t n) { return n <= 128 ? KTAU_SCHEME_NAIVE : network_scheme(n); }
 
-int64_t topk_rounds_len(int64_t len, int k, int64_t* out_len) {
-  // returns the number of rounds; out_len receives the longest list written
-  int64_t rounds = 0, cur = len, longest = 0;
-  do {
-    const int64_t chunks = (cur + kChunk - 1) / kChunk;
-    cur = chunks * k;
-    longest = cur > longest ? cur : longest;
-    ++rounds;
-  } while (cur > k);
-  if (out_len) *out_len = longest;
-  return rounds;
-}
-
 size_t query_scratch_bytes(int64_t nq, int64_t m, int64_t n, int k, bool naive) {
-  int64_t longest = 0;
-  topk_rounds_len(m, k, &longest);
+  (void)k;
   size_t b = ws_layout(nq, n).total;
   if (naive) b = (size_t)round_up((int64_t)(b + bits_bytes(nq, n)), (int64_t)kAlign);
   b += (size_t)round_up(nq * m * 8, (int64_t)kAlign);            // tau
   b += (size_t)round_up(nq * m * 8, (int64_t)kAlign);            // nd
-  b += 2 * (size_t)round_up(nq * longest * (int64_t)sizeof(TopItem), (int64_t)kAlign);
   return b;
 }
 
@@ -264,8 +290,6 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
                  hipStream_t s) {
   if (nq == 0) return KTAU_OK;
   const int64_t m = db.m, n = db.n;
-  int64_t longest = 0;
-  topk_rounds_len(m, k, &longest);
   char* base = (char*)scratch;
   const bool naive = db.scheme == KTAU_SCHEME_NAIVE;
   size_t off = ws_layout(nq, n).total;
@@ -274,10 +298,6 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
   double* tau = (double*)(base + off);
   off += (size_t)round_up(nq * m * 8, (int64_t)kAlign);
   int64_t* nd = (int64_t*)(base + off);
-  off += (size_t)round_up(nq * m * 8, (int64_t)kAlign);
-  TopItem* ia = (TopItem*)(base + off);
-  off += (size_t)round_up(nq * longest * (int64_t)sizeof(TopItem), (int64_t)kAlign);
-  TopItem* ib = (TopItem*)(base + off);
 
   // rank the query rows into the scratch head (its status word is unused:
   // the caller's status word collects NaN reports)
@@ -316,30 +336,9 @@ int launch_query(const DbView& db, const float* Q, int64_t nq, int k, void* scra
   if (e == hipSuccess && composite) e = query_composite(qd, s);
   if (e != hipSuccess) return KTAU_EDEVICE;
 
-  // top-k rounds: tau -> ia -> ib -> ia ...
-  int64_t len = m;
-  const TopItem* src = nullptr;
-  TopItem* dst = ia;
-  bool first = true;
-  for (;;) {
-    const int64_t chunks = (len + kChunk - 1) / kChunk;
-    const int64_t out_len = chunks * k;
-    int cnt = 1;
-    while (cnt < (len < kChunk ? len : kChunk)) cnt <<= 1;
-    while (cnt < k) cnt <<= 1;
-    hipLaunchKernelGGL(topk_round_kernel, dim3((unsigned)chunks, (unsigned)nq), dim3(256),
-                       (size_t)cnt * sizeof(TopItem), s, first ? tau : nullptr, src, len, k, dst,
-                       out_len);
-    if (hipGetLastError() != hipSuccess) return KTAU_EDEVICE;
-    first = false;
-    len = out_len;
-    if (len <= k) break;
-    src = dst;
-    dst = dst == ia ? ib : ia;
-  }
-  const int64_t total = nq * k;
-  hipLaunchKernelGGL(topk_write_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     dst, nq, k, tau, nd, m, idx_out, tau_out, nd_out);
+  // exact top-k, one workgroup per query row
+  hipLaunchKernelGGL(topk_select_kernel, dim3((unsigned)nq), dim3(kSelThreads), 0, s, tau, nd, m,
+                     k, idx_out, tau_out, nd_out);
   return hipGetLastError() == hipSuccess ? KTAU_OK : KTAU_EDEVICE;
 }
 

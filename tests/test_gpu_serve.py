@@ -151,6 +151,25 @@ def _serve_requests(db, Q, sizes, k, concurrent, **cfg):
     return out, stats
 
 
+@pytest.mark.parametrize("k", [1, 29, 45, 250, 400])
+def test_topk_cut_inside_equal_keys(k):
+    """Selection where the k-th result falls inside a group of equal |tau|:
+    10 distinct rows, each repeated 30 times (equal tau for every copy), 20
+    constant rows (NaN, never returned), so that the first k in row order of
+    the boundary group are taken and k = 400 leaves padding."""
+    rng = np.random.default_rng(81)
+    n = 300
+    base = rng.standard_normal((10, n)).astype(np.float32)
+    X = np.repeat(base, 30, axis=0)[rng.permutation(300)]
+    X = np.concatenate([X, np.full((20, n), 3.0, np.float32)])[rng.permutation(320)]
+    X = np.ascontiguousarray(X)
+    Q = np.ascontiguousarray(rng.standard_normal((6, n)).astype(np.float32))
+    Q[1] = base[3]
+    kdb = S.KtauDb(torch.from_numpy(X).cuda())
+    got = {a: b.cpu().numpy() for a, b in S.ktau_query(kdb, torch.from_numpy(Q).cuda(), k).items()}
+    _check_topk(got, oracle.query_topk(X, Q, k))
+
+
 def test_server_merges_different_k():
     # requests with different k merge into one launch of the largest k; each
     # keeps the first k of its rows (a prefix of the longer list)
