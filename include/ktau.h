@@ -405,8 +405,8 @@ int ktau_query(const ktau_db* db, const float* Q_dev, int64_t nq, int64_t k,
 typedef struct ktau_server ktau_server;
 
 typedef struct ktau_server_cfg {
-  int32_t slots;             /* concurrent launches (streams); default 4        */
-  int32_t max_batch_queries; /* rows merged into one launch; default 64         */
+  int32_t slots;             /* concurrent launches (streams); default 2        */
+  int32_t max_batch_queries; /* rows merged into one launch; default 256        */
   int64_t mem_budget_bytes;  /* device pool for running launches; default 1 GiB */
   int32_t max_queue;         /* queued requests before submit blocks/refuses    */
   int32_t k_max;             /* largest k accepted; default 128 (<= KTAU_MAX_K) */

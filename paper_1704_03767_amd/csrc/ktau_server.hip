@@ -233,8 +233,12 @@ extern "C" {
 
 void ktau_server_default_cfg(ktau_server_cfg* c) {
   if (!c) return;
-  c->slots = 4;
-  c->max_batch_queries = 64;
+  // measured on a 20000 x 800 database with requests of 1-64 rows at 0.8 of
+  // saturation: two launches in flight of up to 256 rows gave the highest
+  // saturation and the most requests per launch at a p50 within 10% of the
+  // best
+  c->slots = 2;
+  c->max_batch_queries = 256;
   c->mem_budget_bytes = (int64_t)1 << 30;
   c->max_queue = 4096;
   c->k_max = 128;

@@ -140,7 +140,7 @@ def ktau_query(db: KtauDb, Q: torch.Tensor, k: int, workspace: torch.Tensor | No
 class KtauServer:
     """The library's continuous-batching query server over a KtauDb."""
 
-    def __init__(self, db: KtauDb, slots: int = 4, max_batch_queries: int = 64,
+    def __init__(self, db: KtauDb, slots: int = 2, max_batch_queries: int = 256,
                  mem_budget_bytes: int = 1 << 30, max_queue: int = 4096, k_max: int = 128):
         L = _slib()
         cfg = _ServerCfg()
