@@ -278,7 +278,8 @@ struct Net {
     for (int j = 0; j < KV; ++j) {
       const uint32_t t = bits(v[j]) & 0x00010001u;
       if constexpr (L + 1 < LOGK) {
-        acc_in = __builtin_amdgcn_udot2(vec(t), vec(in_lane_weight(L, j)), acc_in, false);
+        const uint32_t w = in_lane_weight(L, j);
+        if (w != 0u) acc_in = __builtin_amdgcn_udot2(vec(t), vec(w), acc_in, false);
       } else {
         constexpr uint32_t kW = 1u << kWShift;
         const uint32_t w = ((uint32_t)j + kW) | (((uint32_t)(j + KV) + kW) << 16);
@@ -358,11 +359,41 @@ struct Net {
 // Bias of the half-precision keys: the smallest normal f16 pattern.
 constexpr uint32_t kHalfKeyBias = 0x0400u;
 
+// Tag bits held below the rank in the half-precision keys of an N-key
+// network: the most (up to 5) for which padding with a full field,
+// 0x0400 + (N + 1) 2^T - 1, is still a finite f16 pattern (4 for 1024 keys,
+// 1 for 8192).
+constexpr int half_tag_bits(int N) {
+  int t = 1;
+  while (t < 5 && (uint32_t)(N + 1) * (2u << t) + kHalfKeyBias - 1u <= 0x7BFFu) ++t;
+  return t;
+}
+
+// (a & b) ^ c in one v_bitop3_b32, b in a scalar register.
+__device__ __forceinline__ uint32_t and_xor(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x6a" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
 // The same count with keys held as half-precision bit patterns, for groups of
-// at most 8192 keys.  A key 2*rank + tag becomes the positive normal f16
-// pattern 0x0400 + 2*rank + tag (padding 0x7BFE), so that the packed f16
-// minimum orders keys as integers do, and flipping the sign bit reverses the
-// order.  The sign bit then carries two things:
+// at most 8192 keys.  A key is the positive normal f16 pattern
+// 0x0400 + rank * 2^T + field, T = half_tag_bits(N): the rank decides every
+// comparison between different ranks, and the T-bit field below it holds the
+// tags of T levels at once (a tag epoch): bit i is the element's position bit
+// of the epoch's i-th level, taken at the epoch's first level (bits at and
+// above a level's stay fixed until that level's merge).  Equal ranks are then
+// ordered by the current level's tag: earlier levels' tags sit below it, and
+// later levels' tags are equal across a block.  So keys are re-tagged once per
+// epoch, not once per level.  The packed f16 minimum orders the keys as
+// integers do, and flipping the sign bit reverses the order.
+//
+// Level 0 is counted directly (each pair compared before its exchange).  The
+// other levels inside one half of a lane's VGPRs (register stages only) keep
+// every block ascending: a level's first stage pairs each position with its
+// mirror in the block, the rest are half-cleaners, and no sign is used.  From
+// the half stage's level on (its first stage mirrored as well) the sign bit
+// carries two things:
 //   * the orientation of a descending block (in place of the complement);
 //   * a per-stage pattern: in a stage whose partner sits in another lane or
 //     in the other half of the VGPR, the upper partner is held negated, so
@@ -377,15 +408,19 @@ constexpr uint32_t kHalfKeyBias = 0x0400u;
 // high halves stay negated, so the register stages sort them descending: from
 // that level on, a lane's high halves hold its upper K/2 elements in reverse
 // order (element K-1-j in VGPR j).  Register and lane stages pair the same
-// VGPRs under that numbering; later half stages pair VGPR j with VGPR KV-1-j,
-// and the count's position weights follow it.
+// VGPRs under that numbering; half stages pair VGPR j with VGPR KV-1-j (at the
+// half stage's own level that is the mirror of an ascending 64-element
+// block), and the count's position weights follow it.
 
 template <int K, int G>
 struct NetS {
   using B = Net<K, G>;
   static constexpr int KV = B::KV, LOGK = B::LOGK, LOGKV = B::LOGKV, LOGG = B::LOGG;
   static constexpr int LOGN = B::LOGN, N = B::N, kXChunk = B::kXChunk, kWShift = B::kWShift;
-  static_assert(N <= 8192, "keys 0x0400 + 2*rank + tag stay below the padding key 0x7BFE");
+  static_assert(N <= 8192, "keys 0x0400 + rank * 2^T + field stay finite");
+  static_assert(KV >= 2, "level 0 pairs two VGPRs");
+  static constexpr int kT = half_tag_bits(N);
+  static constexpr uint32_t kField = ((1u << kT) - 1u) * 0x00010001u;
   static constexpr uint32_t kSign = 0x80008000u;
   typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
@@ -399,18 +434,41 @@ struct NetS {
   static __device__ __forceinline__ uint32_t fmx(uint32_t a, uint32_t b) {
     return hu(__builtin_elementwise_maximum(hv(a), hv(b)));
   }
-  // min(a, -b); min(a, -(a with its halves swapped)); min(a, -(b with its
-  // halves swapped))
+  // min(a, -b); min(a, -(b with its halves swapped))
   static __device__ __forceinline__ uint32_t fmn_neg(uint32_t a, uint32_t b) {
     return hu(__builtin_elementwise_minimum(hv(a), -hv(b)));
-  }
-  static __device__ __forceinline__ uint32_t fmn_neg_swap(uint32_t a) {
-    const h2 x = hv(a);
-    return hu(__builtin_elementwise_minimum(x, -__builtin_shufflevector(x, x, 1, 0)));
   }
   static __device__ __forceinline__ uint32_t fmn_neg_swapped(uint32_t a, uint32_t b) {
     const h2 y = hv(b);
     return hu(__builtin_elementwise_minimum(hv(a), -__builtin_shufflevector(y, y, 1, 0)));
+  }
+
+  // Tag epochs start at level 1, every kT levels inside a half, at the half
+  // stage's level LOGKV, and every kT levels after it.
+  static constexpr bool epoch_start(int L) {
+    if (L == 1 || L == LOGKV) return true;
+    return L < LOGKV ? (L - 1) % kT == 0 : (L - LOGKV) % kT == 0;
+  }
+  static constexpr int epoch_of(int L) {
+    int s = L;
+    while (!epoch_start(s)) --s;
+    return s;
+  }
+  // Field of an epoch starting at level S < LOGKV (tags inside a half only:
+  // the same in both halves and every lane).
+  static constexpr uint32_t half_field(int S, int j) {
+    const int w = kT < LOGKV - S ? kT : LOGKV - S;
+    return (((uint32_t)j >> S) & ((1u << w) - 1u)) * 0x00010001u;
+  }
+  // Field of an epoch starting at level S >= LOGKV, both halves.
+  static __device__ __forceinline__ uint32_t field_word(int S, int lane, int j) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t e = ((uint32_t)lane << LOGK) | ((uint32_t)h << LOGKV) | (uint32_t)j;
+      c |= ((e >> S) & ((1u << kT) - 1u)) << (16 * h);
+    }
+    return c;
   }
 
   // Stage on element bit k: takes a sign pattern (the upper partner negated)
@@ -429,6 +487,7 @@ struct NetS {
     return ((lane >> (b - LOGK)) & 1) ? kSign : 0u;
   }
 
+  // A stage of a level L >= LOGKV.
   template <int L, int k>
   static __device__ __forceinline__ void stage(uint32_t (&v)[KV], int lane, int plane,
                                                uint32_t* xbuf) {
@@ -441,12 +500,8 @@ struct NetS {
         v[j] = fmn(a, b);
         v[p] = fmx(a, b);
       }
-    } else if constexpr (k == LOGKV && (L == LOGKV || KV == 1)) {
-#pragma unroll
-      for (int j = 0; j < KV; ++j) v[j] = fmn_neg_swap(v[j]);
     } else if constexpr (k == LOGKV) {
-      // the high halves hold their elements in reverse order: VGPR j's low
-      // half meets VGPR KV-1-j's high half and the reverse
+      // VGPR j's low half meets VGPR KV-1-j's high half and the reverse
 #pragma unroll
       for (int j = 0; j < KV / 2; ++j) {
         const uint32_t a = v[j], b = v[KV - 1 - j];
@@ -460,42 +515,28 @@ struct NetS {
 #pragma unroll
         for (int j = 0; j < KV; ++j) v[j] = fmn_neg(v[j], lane_xor<(1 << pb)>(v[j]));
       } else if constexpr (pb == 4 || pb == 5) {
-        if constexpr (KV >= 2) {
 #pragma unroll
-          for (int j = 0; j < KV; j += 2) {
-            uint32_t a = v[j], b = v[j + 1];
-            if constexpr (pb == 4) {
-              auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
-              a = s[0];
-              b = s[1];
-            } else {
-              auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
-              a = s[0];
-              b = s[1];
-            }
-            const uint32_t mn = fmn(a, b), mx = fmx(a, b);
-            if constexpr (pb == 4) {
-              auto s = __builtin_amdgcn_permlane16_swap(mn, mx, false, false);
-              v[j] = s[0];
-              v[j + 1] = s[1];
-            } else {
-              auto s = __builtin_amdgcn_permlane32_swap(mn, mx, false, false);
-              v[j] = s[0];
-              v[j + 1] = s[1];
-            }
-          }
-        } else {
-          const bool lower = ((lane >> lb) & 1) == 0;
-          const uint32_t a = v[0];
-          uint32_t part;
+        for (int j = 0; j < KV; j += 2) {
+          uint32_t a = v[j], b = v[j + 1];
           if constexpr (pb == 4) {
-            auto s = __builtin_amdgcn_permlane16_swap(a, a, false, false);
-            part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
+            auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+            a = s[0];
+            b = s[1];
           } else {
-            auto s = __builtin_amdgcn_permlane32_swap(a, a, false, false);
-            part = lower ? (uint32_t)s[1] : (uint32_t)s[0];
+            auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+            a = s[0];
+            b = s[1];
           }
-          v[0] = lower ? fmn(a, part) : fmx(a, part);
+          const uint32_t mn = fmn(a, b), mx = fmx(a, b);
+          if constexpr (pb == 4) {
+            auto s = __builtin_amdgcn_permlane16_swap(mn, mx, false, false);
+            v[j] = s[0];
+            v[j + 1] = s[1];
+          } else {
+            auto s = __builtin_amdgcn_permlane32_swap(mn, mx, false, false);
+            v[j] = s[0];
+            v[j + 1] = s[1];
+          }
         }
       } else {
 #pragma unroll
@@ -512,8 +553,8 @@ struct NetS {
     }
   }
 
-  // Stages k .. 0 of a level; `cur` is the element bit the current sign
-  // pattern is keyed on (-1: none).
+  // Stages k .. 0 of a level L >= LOGKV; `cur` is the element bit the current
+  // sign pattern is keyed on (-1: none).
   template <int L, int k, int cur>
   static __device__ __forceinline__ void stages_down(uint32_t (&v)[KV], int lane, int plane,
                                                      uint32_t* xbuf) {
@@ -527,9 +568,9 @@ struct NetS {
     if constexpr (k > 0) stages_down<L, k - 1, want>(v, lane, plane, xbuf);
   }
 
-  // Sign bit of element (lane, j, h) at the start of level L (orientation,
-  // bit L+1, xor the pattern of the level's first stage) and at its end (the
-  // half stage of levels L >= LOGKV leaves the high halves negated).
+  // Sign bit of element (lane, j, h) at the start of level L >= LOGKV
+  // (orientation, bit L+1, xor the pattern of the level's first stage) and
+  // at its end (the half stage leaves the high halves negated).
   template <int L>
   static __device__ __forceinline__ uint32_t sign_start(int lane, int j, int h) {
     const uint32_t desc = L + 1 < LOGN ? B::ebit(lane, j, h, L + 1) : 0u;
@@ -538,68 +579,101 @@ struct NetS {
   template <int L>
   static __device__ __forceinline__ uint32_t sign_end(int lane, int j, int h) {
     const uint32_t desc = L + 1 < LOGN ? B::ebit(lane, j, h, L + 1) : 0u;
-    return desc ^ (L >= LOGKV ? (uint32_t)h : 0u);
+    return desc ^ (uint32_t)h;
   }
-  // Tag (bit 0) and sign (bit 15) of each half of VGPR j at the start of
-  // level 0, the keys carrying neither.
-  static __device__ __forceinline__ uint32_t start_const(int lane, int j) {
+  // Sign words: at the start of level LOGKV (from unsigned keys), and the
+  // flips from the end of level L to the start of level L+1.
+  static __device__ __forceinline__ uint32_t entry_signs(int lane, int j) {
+    return (sign_start<LOGKV>(lane, j, 0) << 15) | (sign_start<LOGKV>(lane, j, 1) << 31);
+  }
+  template <int L>
+  static __device__ __forceinline__ uint32_t flips(int lane, int j) {
     uint32_t c = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
-      c |= (B::ebit(lane, j, h, 0) | (sign_start<0>(lane, j, h) << 15)) << (16 * h);
+      c |= (sign_end<L>(lane, j, h) ^ sign_start<L + 1>(lane, j, h)) << (15 + 16 * h);
     return c;
   }
-  // From the end of level L to the start of L+1: with t the current tag
-  // bits, v ^ t ^ retag_const sets tag bit L+1 and flips the sign where it
-  // changes.
-  template <int L>
-  static __device__ __forceinline__ uint32_t retag_const(int lane, int j) {
+
+  // Level 0: each pair (VGPRs j, j+1, both halves) counted, then exchanged.
+  static __device__ __forceinline__ uint32_t level0(uint32_t (&v)[KV]) {
+    constexpr uint32_t kOnes = 0x00010001u;
     uint32_t c = 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t flip = sign_end<L>(lane, j, h) ^ sign_start<L + 1>(lane, j, h);
-      c |= (B::ebit(lane, j, h, L + 1) | (flip << 15)) << (16 * h);
+    for (int j = 0; j < KV; j += 2) {
+      const u16x2 a = vec(v[j]), b = vec(v[j + 1]);
+      c = __builtin_amdgcn_udot2(pmin(__builtin_elementwise_sub_sat(a, b), vec(kOnes)), vec(kOnes),
+                                 c, false);
+      asm volatile("" : "+v"(c));
+      v[j] = bits(pmin(a, b));
+      v[j + 1] = bits(pmax(a, b));
     }
     return c;
   }
 
-  // Key position weights of the count (see Net): inside a lane, VGPR j's
-  // halves at ascending positions of their merged block.
-  static constexpr uint32_t in_lane_weight(int L, int j) {
-    uint32_t w = 0;
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t e = ((uint32_t)h << LOGKV) | (uint32_t)j;
-      const uint32_t m2s = (2u << L) - 1u;
-      const uint32_t pos = e & m2s;
-      const uint32_t desc = (e >> (L + 1)) & 1u;
-      w |= (desc ? m2s - pos : pos) << (16 * h);
+  // Levels 1 .. LOGKV-1, inside a half: ascending blocks of 2^(L+1) VGPRs.
+  // In an ascending block of 2s merged from two of s, the pairs counted are
+  // s*s + s(s-1)/2 less the sum of the positions of the second block's
+  // elements (added in constant_part).
+  template <int L>
+  static __device__ __forceinline__ void half_levels(uint32_t (&v)[KV], uint32_t& total) {
+    if constexpr (L < LOGKV) {
+      if constexpr (L > 1 && epoch_start(L)) {
+#pragma unroll
+        for (int j = 0; j < KV; ++j) v[j] = (v[j] & ~kField) | half_field(L, j);
+      }
+      constexpr int m = (2 << L) - 1;
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        if ((j >> L) & 1) continue;
+        const u16x2 a = vec(v[j]), b = vec(v[j ^ m]);
+        v[j] = bits(pmin(a, b));
+        v[j ^ m] = bits(pmax(a, b));
+      }
+#pragma unroll
+      for (int k = L - 1; k >= 0; --k) {
+#pragma unroll
+        for (int j = 0; j < KV; ++j) {
+          if ((j >> k) & 1) continue;
+          const u16x2 a = vec(v[j]), b = vec(v[j | (1 << k)]);
+          v[j] = bits(pmin(a, b));
+          v[j | (1 << k)] = bits(pmax(a, b));
+        }
+      }
+      constexpr int tb = L - epoch_of(L);
+      uint32_t acc = 0;
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        const uint32_t w = (uint32_t)(j & m);
+        if (w == 0u) continue;
+        acc = __builtin_amdgcn_udot2(vec(v[j] & (0x00010001u << tb)), vec(w * 0x00010001u), acc,
+                                     false);
+        asm volatile("" : "+v"(acc));
+      }
+      total -= acc >> tb;
+      half_levels<L + 1>(v, total);
     }
-    return w;
   }
 
+  // Levels L .. kEnd-1 (L >= LOGKV): stages, count, and the step to the next
+  // level (sign flips, and a new field where an epoch starts).  Without the
+  // top level the first half's keys end with field and sign cleared.
   template <int L, int kEnd>
   static __device__ __forceinline__ void levels(uint32_t (&v)[KV], int lane, int plane,
-                                                uint32_t* xbuf, uint32_t& acc_in,
-                                                uint32_t& total) {
+                                                uint32_t* xbuf, uint32_t& total) {
     stages_down<L, L, patterned(L) ? L : -1>(v, lane, plane, xbuf);
+    constexpr int tb = L - epoch_of(L);
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < KV; ++j) {
-      const uint32_t t = v[j] & 0x00010001u;
-      if constexpr (L + 1 < LOGK) {
-        acc_in = __builtin_amdgcn_udot2(vec(t), vec(in_lane_weight(L, j)), acc_in, false);
-        asm volatile("" : "+v"(acc_in));
-      } else {
-        // the half stage left the high halves negated: descending over j
-        constexpr uint32_t kW = 1u << kWShift;
-        const uint32_t w = ((uint32_t)j + kW) | (((uint32_t)(K - 1 - j) + kW) << 16);
-        acc = __builtin_amdgcn_udot2(vec(t), vec(w), acc, false);
-        asm volatile("" : "+v"(acc));
-      }
-      // the re-tag word depends on the lane once bit L+2 is a lane bit
-      if constexpr (L + 1 < LOGN) v[j] = xor3<(L + 2 < LOGK)>(v[j], t, retag_const<L>(lane, j));
+      // the half stage left the high halves negated: descending over j
+      constexpr uint32_t kW = 1u << kWShift;
+      const uint32_t w = ((uint32_t)j + kW) | (((uint32_t)(K - 1 - j) + kW) << 16);
+      acc = __builtin_amdgcn_udot2(vec(v[j] & (0x00010001u << tb)), vec(w), acc, false);
+      asm volatile("" : "+v"(acc));
     }
-    if constexpr (L + 1 >= LOGK) {
+    acc >>= tb;
+    {
       // the lane lies inside one block of 2s, at ascending offset base of
       // its oriented keys; a descending block's key order is the reverse
       constexpr uint32_t m2s = (2u << L) - 1u;
@@ -608,13 +682,26 @@ struct NetS {
       const uint32_t desc = (L + 1 < LOGN) ? (uint32_t)(lane >> (L + 1 - LOGK)) & 1u : 0u;
       total -= desc ? (m2s - base) * nraw - rsum : base * nraw + rsum;
     }
-    if constexpr (L + 1 < kEnd) levels<L + 1, kEnd>(v, lane, plane, xbuf, acc_in, total);
+    if constexpr (L + 1 < kEnd) {
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        if constexpr (epoch_start(L + 1))
+          v[j] = and_xor(v[j], ~kField, field_word(L + 1, lane, j) | flips<L>(lane, j));
+        else
+          v[j] ^= flips<L>(lane, j);
+      }
+      levels<L + 1, kEnd>(v, lane, plane, xbuf, total);
+    } else if constexpr (L + 1 < LOGN) {
+#pragma unroll
+      for (int j = 0; j < KV; ++j) v[j] &= ~(kField | kSign);
+    }
   }
 
-  // Over all levels, sum over blocks of s*s + s(s-1)/2.
+  // Over levels 1 .. LOGN-1, sum over blocks of s*s + s(s-1)/2 (level 0 is
+  // counted directly).
   static constexpr uint32_t constant_part() {
     uint64_t c = 0;
-    for (int L = 0; L < LOGN; ++L) {
+    for (int L = 1; L < LOGN; ++L) {
       const uint64_t s = 1ull << L;
       c += ((uint64_t)N / (2 * s)) * (s * s + s * (s - 1) / 2);
     }
@@ -622,11 +709,8 @@ struct NetS {
   }
   static constexpr uint32_t top_const() { return B::top_const(); }
 
-  // Bias of the first half's keys after the network without its top level:
-  // they are 0x0400 + 2*rank.
-  static constexpr uint32_t kKeyBias = kHalfKeyBias;
-
-  // As Net::count_split, from the same packed keys 2*rank (padding 0xFFFE).
+  // As Net::count_split, from the same packed keys 2*rank (padding 0xFFFE);
+  // without the top level the first half's keys end as 0x0400 + rank * 2^kT.
   template <bool kTop>
   static __device__ __forceinline__ uint32_t count_split(u16x2 (&key)[KV], int plane,
                                                          uint32_t* xbuf) {
@@ -635,16 +719,23 @@ struct NetS {
     // and held, or spilled, across it)
     asm volatile("" : "+v"(plane));
     const int lane = B::logical_lane(plane);
+    constexpr uint32_t kScale = (1u << (kT - 1)) * 0x00010001u;
     uint32_t v[KV];
 #pragma unroll
     for (int j = 0; j < KV; ++j) {
-      // the bias and the level-0 tag and sign bits (all clear in the clamped
-      // key) in one packed add
-      v[j] = bits(pmin(key[j], vec(0x77FE77FEu)) + vec(0x04000400u | start_const(lane, j)));
+      // 0x0400 + rank * 2^kT + the first epoch's field, padding at rank N
+      const u16x2 r = pmin(key[j], vec((uint32_t)(2 * N) * 0x00010001u));
+      v[j] = bits(r * vec(kScale) + vec(0x04000400u | half_field(1, j)));
     }
-    uint32_t acc_in = 0, total = 0;
-    levels<0, kTop ? LOGN : LOGN - 1>(v, lane, plane, xbuf, acc_in, total);
-    total -= acc_in;
+    uint32_t total = level0(v);
+    half_levels<1>(v, total);
+    {
+      // into the half stage's level: its epoch's field and the signs
+#pragma unroll
+      for (int j = 0; j < KV; ++j)
+        v[j] = and_xor(v[j], ~kField, field_word(LOGKV, lane, j) | entry_signs(lane, j));
+    }
+    levels<LOGKV, kTop ? LOGN : LOGN - 1>(v, lane, plane, xbuf, total);
     if (plane == 0) total += kTop ? constant_part() : constant_part() - top_const();
 #pragma unroll
     for (int j = 0; j < KV; ++j) key[j] = vec(v[j]);

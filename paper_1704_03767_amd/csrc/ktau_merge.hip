@@ -439,9 +439,9 @@ __device__ bool pair_merge(const RankView& ry, int64_t y, const RankView& rx, in
     u16x2 key[KV];
     if (active) merge_gather<K>(row, ru_v.perm + u * ld, k0, ld, !kWide, key);
     if (closed && active && k0 < s_top) {
-      uint32_t gk[kTopGroups] = {}, gm[kTopGroups] = {};
-      top_groups(rv_v, v, ngroups, 0u, gk, gm);
-      share += top_share<K, 0u>(key, ngroups, gk, gm, eqs);
+      TopGroups tg;
+      top_groups(rv_v, v, ngroups, n, 0u, 1, tg);
+      share += top_share<K, 0u, 1>(key, ngroups, tg, eqs);
     }
     if (pass == 0 && (kWide || n1u != 0)) {
       // v' in u order replaces the rank row

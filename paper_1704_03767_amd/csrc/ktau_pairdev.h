@@ -323,14 +323,26 @@ constexpr int kTopGroups = 2;
 // minrank(a) = d(a) + sum_g (m_g - 1) [d(a) > d_g] and
 // ties(A) = sum_g C(#{a in A : d(a) = d_g}, 2).  This returns the lane's
 // share of the first sum (0 outside A) and, in eqs, its per-group counts of
-// d(a) = d_g (16 bits per group).  The keys are kBias + 2d; gk holds
-// kBias + 2 d_g in both halves, gm the m_g - 1.
-template <int K, uint32_t kBias>
+// d(a) = d_g (16 bits per group).  The keys are kBias + d * 2^kShift
+// (kShift >= 1), and the lane's K keys all belong to samples (no padding).
+//
+// Per group, with g = kBias + d_g * 2^kShift (keys differ from it by
+// multiples of at least 2): at the lowest dense rank no key lies below the
+// group, so sat(g + 1 - key) is 1 at the group and 0 above it and
+// #above = K - #at; at the highest none lies above, and sat(key - (g - 1)) is
+// 1 at the group and 0 below it; otherwise f = min(sat(key - (g - 1)), 2) is
+// 0 below, 1 at and 2 above, and sum f = #at + 2 #above,
+// sum f^2 = #at + 4 #above.
+enum : int { kGroupInner = 0, kGroupLowest = 1, kGroupHighest = 2 };
+struct TopGroups {
+  uint32_t op[kTopGroups] = {};     // the comparison operand above, both halves
+  uint32_t gm[kTopGroups] = {};     // m_g - 1
+  int edge[kTopGroups] = {};        // kGroupInner / kGroupLowest / kGroupHighest
+};
+
+template <int K, uint32_t kBias, int kShift>
 __device__ __forceinline__ uint32_t top_share(const bitonic::u16x2 (&key)[K / 2], int ngroups,
-                                              const uint32_t (&gk)[kTopGroups],
-                                              const uint32_t (&gm)[kTopGroups],
-                                              uint32_t& eqs) {
-  using bitonic::bits;
+                                              const TopGroups& tg, uint32_t& eqs) {
   using bitonic::u16x2;
   using bitonic::vec;
   constexpr int KV = K / 2;
@@ -338,34 +350,48 @@ __device__ __forceinline__ uint32_t top_share(const bitonic::u16x2 (&key)[K / 2]
   uint32_t s2 = 0;
 #pragma unroll
   for (int j = 0; j < KV; ++j) s2 = __builtin_amdgcn_udot2(key[j], vec(kOnes), s2, false);
-  uint32_t share = (s2 - (uint32_t)K * kBias) >> 1;
+  uint32_t share = (s2 - (uint32_t)K * kBias) >> kShift;
   eqs = 0;
 #pragma unroll
   for (int g = 0; g < kTopGroups; ++g) {
     if (g >= ngroups) break;
-    // f = 0, 1 or 2 for a key below, at or above 2 d_g (keys are even, so
-    // (key | 1) - 2 d_g is 1 at the group and at least 3 above it)
-    uint32_t a1 = 0, a2 = 0;
+    const u16x2 op = vec(tg.op[g]);
+    uint32_t at = 0, above = 0;
+    if (tg.edge[g] == kGroupLowest) {
 #pragma unroll
-    for (int j = 0; j < KV; ++j) {
-      const u16x2 f = bitonic::pmin(__builtin_elementwise_sub_sat(vec(bits(key[j]) | kOnes), vec(gk[g])),
-                                    vec(0x00020002u));
-      a1 = __builtin_amdgcn_udot2(f, vec(kOnes), a1, false);   // eq + 2 gt
-      a2 = __builtin_amdgcn_udot2(f, f, a2, false);            // eq + 4 gt
+      for (int j = 0; j < KV; ++j)
+        at = __builtin_amdgcn_udot2(__builtin_elementwise_sub_sat(op, key[j]), vec(kOnes), at,
+                                    false);
+      above = (uint32_t)K - at;
+    } else if (tg.edge[g] == kGroupHighest) {
+#pragma unroll
+      for (int j = 0; j < KV; ++j)
+        at = __builtin_amdgcn_udot2(__builtin_elementwise_sub_sat(key[j], op), vec(kOnes), at,
+                                    false);
+    } else {
+      uint32_t a1 = 0, a2 = 0;
+#pragma unroll
+      for (int j = 0; j < KV; ++j) {
+        const u16x2 f = bitonic::pmin(__builtin_elementwise_sub_sat(key[j], op),
+                                      vec(0x00020002u));
+        a1 = __builtin_amdgcn_udot2(f, vec(kOnes), a1, false);   // at + 2 above
+        a2 = __builtin_amdgcn_udot2(f, f, a2, false);            // at + 4 above
+      }
+      at = 2 * a1 - a2;
+      above = (a2 - a1) >> 1;
     }
-    share += gm[g] * ((a2 - a1) >> 1);
-    eqs |= (2 * a1 - a2) << (16 * g);
+    share += tg.gm[g] * above;
+    eqs |= at << (16 * g);
   }
   return share;
 }
 
-// The tie groups of row v (at most kTopGroups of them, ngroups in all) as
-// top_share takes them: gk = kBias + 2 d_g in both halves (d_g the group's
-// dense rank: its run start less the surplus m - 1 of the runs before it),
-// gm = m_g - 1.
-__device__ __forceinline__ void top_groups(const RankView& rv_v, int64_t v, int ngroups,
-                                           uint32_t kBias, uint32_t (&gk)[kTopGroups],
-                                           uint32_t (&gm)[kTopGroups]) {
+// The tie groups of row v (at most kTopGroups of them, ngroups in all, n
+// samples) as top_share takes them: d_g is the group's dense rank (its run
+// start less the surplus m - 1 of the runs before it); the highest dense
+// rank is n - 1 less the surplus of all runs.
+__device__ __forceinline__ void top_groups(const RankView& rv_v, int64_t v, int ngroups, int n,
+                                           uint32_t kBias, int kShift, TopGroups& tg) {
   if (ngroups <= 0) return;
   const uint64_t* rl = rv_v.runs + v * (rv_v.ld / 2);
   uint32_t st[kTopGroups], ln[kTopGroups];
@@ -382,11 +408,15 @@ __device__ __forceinline__ void top_groups(const RankView& rv_v, int64_t v, int 
     st[1] = ts;
     ln[1] = tl;
   }
-  const uint32_t d0 = st[0], d1 = st[1] - (ln[0] - 1u);
-  gk[0] = (kBias + 2u * d0) * 0x00010001u;
-  gk[1] = (kBias + 2u * d1) * 0x00010001u;
-  gm[0] = ln[0] - 1u;
-  gm[1] = ln[1] - 1u;
+  const uint32_t d[kTopGroups] = {st[0], st[1] - (ln[0] - 1u)};
+  const uint32_t dmax = (uint32_t)n - 1u - (ln[0] - 1u) - (ln[1] - 1u);
+#pragma unroll
+  for (int g = 0; g < kTopGroups; ++g) {
+    const uint32_t k = kBias + (d[g] << kShift);
+    tg.gm[g] = ln[g] - 1u;
+    tg.edge[g] = d[g] == 0u ? kGroupLowest : d[g] == dmax ? kGroupHighest : kGroupInner;
+    tg.op[g] = (tg.edge[g] == kGroupLowest ? k + 1u : k - 1u) * 0x00010001u;
+  }
 }
 
 // n_d and n3 of one pair from its gathered keys: the direct in-run tie count
@@ -409,6 +439,7 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
   constexpr bool kHalf = G <= 32 && K * G <= 8192;
   using Net = std::conditional_t<kHalf, bitonic::NetS<K, G>, bitonic::Net<K, G>>;
   constexpr uint32_t kBias = kHalf ? bitonic::kHalfKeyBias : 0u;
+  constexpr int kShift = kHalf ? bitonic::half_tag_bits(K * G) : 1;
   constexpr int KV = K / 2;
   const int64_t ld = ru_v.ld;
   uint32_t xin = 0, tie = 0;
@@ -462,9 +493,9 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
   if (pad_half || closed) share = Net::template count_split<false>(key, lane, xbuf) - xin;
   else share = Net::template count_split<true>(key, lane, xbuf) - xin;
   if (closed) {
-    uint32_t gk[kTopGroups] = {}, gm[kTopGroups] = {};
-    top_groups(rv_v, v, ngroups, kBias, gk, gm);
-    const uint32_t t = top_share<K, kBias>(key, ngroups, gk, gm, eqs);
+    TopGroups tg;
+    top_groups(rv_v, v, ngroups, n, kBias, kShift, tg);
+    const uint32_t t = top_share<K, kBias, kShift>(key, ngroups, tg, eqs);
     if (bitonic::Net<K, G>::logical_lane(lane) < G / 2) share += t;
     else eqs = 0;
   }
@@ -508,26 +539,36 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
   const bool in_row = k0 + K <= ld;
   uint16_t* row = (uint16_t*)lds;
   uint32_t* xbuf = lds + FL::kRowWords;
-  // stage v's rank row in LDS
-  if (in_row) {
+  // stage v's rank row in LDS (slots past the row get the padding key)
+  if constexpr (K >= 8) {
+    // 16-byte chunks dealt round-robin to the group's lanes, so that one
+    // store instruction covers consecutive chunks (no bank conflicts)
+    const uint4* src = (const uint4*)(rv_v.rank + v * ld);
+    uint4* dst = (uint4*)row;
+#pragma unroll
+    for (int i = 0; i < K / 8; ++i) {
+      const int c = lane + G * i;
+      dst[c] = 8 * c < ld ? src[c] : make_uint4(0xFFFEFFFEu, 0xFFFEFFFEu, 0xFFFEFFFEu, 0xFFFEFFFEu);
+    }
+  } else {
     uint32_t w[KV];
-    load_words<K>(rv_v.rank + v * ld + k0, w);
+    if (in_row) {
+      load_words<K>(rv_v.rank + v * ld + k0, w);
+    } else {
+#pragma unroll
+      for (int i = 0; i < KV; ++i) w[i] = 0xFFFEFFFEu;
+    }
     store_words<K>(row + k0, w);
   }
-  // workspace perm entries are byte offsets into a rank row (2 x sample)
+  // workspace perm entries are byte offsets into a rank row (2 x sample); a
+  // lane wholly past the row gathers its own (padding) slots
   uint32_t pw[KV];
   if (in_row) {
     load_words<K>(ru_v.perm + u * ld + k0, pw);
   } else {
-    // a lane wholly past the row: its own slots of the LDS row get the
-    // padding key and it gathers them
-    uint32_t w[KV];
 #pragma unroll
-    for (int i = 0; i < KV; ++i) {
-      w[i] = 0xFFFEFFFEu;
+    for (int i = 0; i < KV; ++i)
       pw[i] = (uint32_t)(2 * (k0 + 2 * i)) | ((uint32_t)(2 * (k0 + 2 * i + 1)) << 16);
-    }
-    store_words<K>(row + k0, w);
   }
   group_sync<G>();
   u16x2 key[KV];
