@@ -189,8 +189,9 @@ int ktau_allpairs_noalloc(const float* X_dev, int64_t m, int64_t n, ktau_pair_ou
  * order) from a workspace prepared for the same (m, n): Sec. 3.2 Steps 1-5
  * per pair with the per-row halves taken from the workspace; scheme < 0 and
  * q <= 0 pick the defaults (ktau_plain_default_scheme(n); tile edge 16 for
- * KTAU_SCHEME_NAIVE, else 8 for n <= 4096, 4 for n <= 16384, 2 beyond; the
- * merge schemes take pairs in job order and ignore q).  Errors as
+ * KTAU_SCHEME_NAIVE, else for n <= 4096 16 from m = 8192 rows on and 8 below,
+ * 4 for n <= 16384, 2 beyond; the merge schemes take pairs in job order and
+ * ignore q).  Errors as
  * ktau_allpairs_range, plus KTAU_EINVAL for a scheme that cannot hold n. */
 int ktau_prepare(const float* X_dev, int64_t m, int64_t n, int64_t* out_n1_dev,
                  void* workspace_dev, size_t ws_bytes, void* stream);

@@ -137,7 +137,7 @@ int check_pairs(int64_t m, int64_t n, int64_t& J_begin, int64_t& J_end, int& sch
   } else if (scheme < 0 || scheme >= kNumSchemes || scheme_capacity(scheme) < n) {
     return KTAU_EINVAL;
   }
-  if (q <= 0) q = scheme == KTAU_SCHEME_NAIVE ? kBitsQ : (int)default_q(n);
+  if (q <= 0) q = scheme == KTAU_SCHEME_NAIVE ? kBitsQ : (int)plain_q(m, n);
   if (q < 1 || q > 64) return KTAU_EINVAL;
   return KTAU_OK;
 }

@@ -197,6 +197,8 @@ int network_scheme(int64_t n);
 // Default tile edge: 8 up to n = 4096; longer rows take one 256-lane block per
 // pair and are few (m is small next to n), so smaller tiles spread them.
 int default_q(int64_t n);
+// Tile edge of a plain launch of m rows (default_q, or 16 for large m).
+int plain_q(int64_t m, int64_t n);
 
 // Comparisons the direct in-run tie count may spend on one pair (about the
 // cost of a second sort); rows whose n1 exceeds it are "heavy", and pairs of

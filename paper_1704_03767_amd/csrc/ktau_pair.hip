@@ -340,6 +340,10 @@ int default_scheme(int64_t n) { return n <= 4096 ? network_scheme(n) : kMergeK64
 
 int default_q(int64_t n) { return n <= 4096 ? 8 : n <= 16384 ? 4 : 2; }
 
+// Plain launches know m: from 8192 rows on, 16 x 16 tiles (half the row
+// fetches of 8 x 8, and still ample tiles to fill the chip).
+int plain_q(int64_t m, int64_t n) { return n <= 4096 && m >= 8192 ? 16 : default_q(n); }
+
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
   hipError_t e;
 #define KTAU_CASE(S, K, G) \

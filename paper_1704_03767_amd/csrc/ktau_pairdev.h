@@ -310,6 +310,9 @@ __device__ __forceinline__ void gather_keys(const uint16_t* row, const uint32_t 
 // Tie groups of v up to which the top level's count is taken from global
 // ranks instead of the network's last merge.
 constexpr int kTopGroups = 2;
+// Tie runs of u up to which a lane checks whether its positions meet one
+// before writing them for the in-run walk.
+constexpr int kFewRuns = 4;
 
 // The last merge's count without the merge.  With A the first N/2 positions
 // of u's order and B the rest, the last merge counts the pairs (a in A, b in
@@ -444,9 +447,26 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
   const int64_t ld = ru_v.ld;
   uint32_t xin = 0, tie = 0;
   if (n1u != 0) {
-    // 2 v' in u order replaces the rank row once every lane has gathered
+    // 2 v' in u order replaces the rank row once every lane has gathered;
+    // only the in-run positions are read from it, so with few runs a lane
+    // whose positions meet none of them skips its store (the lanes' blocks
+    // are 2K bytes apart, so their stores contend for the same LDS banks)
+    const uint64_t* rl = ru_v.runs + u * (ld / 2);
+    const int nr = ru_v.nruns[u];
+    bool meets = true;
+    if (nr <= kFewRuns) {
+      meets = false;
+#pragma unroll
+      for (int r = 0; r < kFewRuns; ++r) {
+        if (r < nr) {
+          const uint64_t e = rl[r];
+          const int st = (int)(e & 0xFFFFu), len = (int)((e >> 16) & 0xFFFFu) + 1;
+          meets |= st < k0 + K && st + len > k0;
+        }
+      }
+    }
     group_sync<G>();
-    if (in_row) {
+    if (in_row && meets) {
       uint32_t w[KV];
       if constexpr (KV == 1) {
         w[0] = bitonic::bits(key[0]);
@@ -466,8 +486,6 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
     // The n1_u pairs of positions inside one tie run of u (Step 2), split
     // evenly into 2G stretches; lane l walks stretches l and l + G side by
     // side so that the LDS loads of the two walks overlap.
-    const uint64_t* rl = ru_v.runs + u * (ld / 2);
-    const int nr = ru_v.nruns[u];
     const uint32_t total = (uint32_t)n1u;
     const uint32_t per = (total + 2 * G - 1) / (2 * G);
     const uint32_t p0 = (uint32_t)lane * per, p1 = (uint32_t)(lane + G) * per;
@@ -545,10 +563,20 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
     // store instruction covers consecutive chunks (no bank conflicts)
     const uint4* src = (const uint4*)(rv_v.rank + v * ld);
     uint4* dst = (uint4*)row;
+    if (K * G <= ld) {
+      // every chunk inside the row: all loads in flight, then the stores
+      uint4 w[K / 8];
 #pragma unroll
-    for (int i = 0; i < K / 8; ++i) {
-      const int c = lane + G * i;
-      dst[c] = 8 * c < ld ? src[c] : make_uint4(0xFFFEFFFEu, 0xFFFEFFFEu, 0xFFFEFFFEu, 0xFFFEFFFEu);
+      for (int i = 0; i < K / 8; ++i) w[i] = src[lane + G * i];
+#pragma unroll
+      for (int i = 0; i < K / 8; ++i) dst[lane + G * i] = w[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < K / 8; ++i) {
+        const int c = lane + G * i;
+        dst[c] = 8 * c < ld ? src[c]
+                            : make_uint4(0xFFFEFFFEu, 0xFFFEFFFEu, 0xFFFEFFFEu, 0xFFFEFFFEu);
+      }
     }
   } else {
     uint32_t w[KV];
