@@ -555,7 +555,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scheme", default=None, help="force a pair scheme (name or id)")
-    ap.add_argument("--q", type=int, default=0, help="tile edge (default 8)")
+    ap.add_argument("--q", type=int, default=0, help="tile edge (default: the library's plain default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--plain-only", action="store_true", help="time only the plain form")
@@ -695,7 +695,7 @@ def main() -> int:
             "input_sha256": synth.sha256(X)[:16],
         },
         "plain": {"ms_per_step": ms_plain, "pairs_per_s": P / (ms_plain * 1e-3),
-                  "scheme": K.ktau_scheme_names()[scheme], "q": args.q or 8,
+                  "scheme": K.ktau_scheme_names()[scheme], "q": args.q or K.ktau_plain_default_q(m, n),
                   "prepass_ms": prep_ms, "pair_kernel_ms": pair_ms,
                   "pair_kernel_ms_median": float(np.median(pair_all)),
                   "pair_kernel_ms_min": float(np.min(pair_all)),

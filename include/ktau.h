@@ -242,6 +242,9 @@ int ktau_default_scheme(int64_t n);
 /* The scheme the plain calls pick for n: KTAU_SCHEME_NAIVE where it measured
  * faster than the network, else ktau_default_scheme(n). */
 int ktau_plain_default_scheme(int64_t n);
+/* The tile edge the plain calls pick for m rows of n samples with scheme
+ * ktau_plain_default_scheme(n) (Sec. 4.2, Eq. 11-14: q x q tiles of pairs). */
+int ktau_plain_default_q(int64_t m, int64_t n);
 
 /* ktau_allpairs (J_begin < 0) or ktau_allpairs_range (J_begin >= 0) with the
  * scheme (a numbered scheme or KTAU_SCHEME_NAIVE) and tile edge q (1..64,

@@ -216,6 +216,9 @@ int64_t ktau_scheme_capacity(int scheme) {
 }
 int ktau_default_scheme(int64_t n) { return default_scheme(n); }
 int ktau_plain_default_scheme(int64_t n) { return plain_default_scheme(n); }
+int ktau_plain_default_q(int64_t m, int64_t n) {
+  return plain_default_scheme(n) == KTAU_SCHEME_NAIVE ? kBitsQ : (int)plain_q(m, n);
+}
 
 int ktau_prepare(const float* X, int64_t m, int64_t n, int64_t* out_n1, void* ws,
                  size_t ws_bytes, void* stream) {

@@ -263,6 +263,9 @@ hipError_t launch_prepass_batch(const MatDesc* descs_dev, int64_t count, int64_t
 // Main pair kernel over all tiles (tiles = true) or over jobs
 // [J_begin, J_end), then the heavy-row pass and the composite pass.
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s);
+// The tile kernel alone (one workgroup per tile, band schedule) of a network
+// scheme: its pairs past the tie budget are left to the composite pass.
+hipError_t launch_pair_tiles(const MatDesc& d, hipStream_t s);
 
 // Merge-scheme pair kernel over jobs [J_begin, J_end) of one matrix (pairs of
 // two heavy rows are left to the composite pass, as in the network schemes).

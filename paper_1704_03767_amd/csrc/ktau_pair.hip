@@ -344,6 +344,16 @@ int default_q(int64_t n) { return n <= 4096 ? 8 : n <= 16384 ? 4 : 2; }
 // fetches of 8 x 8, and still ample tiles to fill the chip).
 int plain_q(int64_t m, int64_t n) { return n <= 4096 && m >= 8192 ? 16 : default_q(n); }
 
+hipError_t launch_pair_tiles(const MatDesc& d, hipStream_t s) {
+  switch (d.scheme) {
+#define KTAU_CASE(S, K, G) \
+  case S: return launch_tiles_t<K, G>(d, s);
+    KTAU_FOR_EACH_SCHEME(KTAU_CASE)
+#undef KTAU_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_pairs_plain(const MatDesc& d, bool tiles, hipStream_t s) {
   hipError_t e;
 #define KTAU_CASE(S, K, G) \

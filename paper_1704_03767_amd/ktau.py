@@ -69,6 +69,7 @@ def _declare(lib):
         "ktau_scheme_capacity": ([i32], i64),
         "ktau_default_scheme": ([i64], i32),
         "ktau_plain_default_scheme": ([i64], i32),
+        "ktau_plain_default_q": ([i64, i64], i32),
         "ktau_perm_workspace_size": ([i64, i64, i64], sz),
         "ktau_probe_threads": ([], i32),
         "ktau_probe_valu_ops_per_iter": ([], i32),
@@ -159,6 +160,10 @@ def ktau_default_scheme(n: int) -> int:
 
 def ktau_plain_default_scheme(n: int) -> int:
     return int(lib().ktau_plain_default_scheme(int(n)))
+
+
+def ktau_plain_default_q(m: int, n: int) -> int:
+    return int(lib().ktau_plain_default_q(int(m), int(n)))
 
 
 def scheme_name(scheme: int) -> str:

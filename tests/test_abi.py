@@ -137,6 +137,18 @@ def test_workspace_holds_the_bit_sets():
     assert K.scheme_id(K.NAIVE_SCHEME_NAME) == K.KTAU_SCHEME_NAIVE
 
 
+def test_plain_default_tile_edge():
+    # 16 x 16 tiles from 8192 rows on (networks up to 4096 samples), 8 x 8
+    # below; the bit-set count keeps 16; longer rows take smaller tiles
+    assert K.ktau_plain_default_q(16384, 1024) == 16
+    assert K.ktau_plain_default_q(17941, 353) == 16
+    assert K.ktau_plain_default_q(8191, 1024) == 8
+    assert K.ktau_plain_default_q(4096, 512) == 8
+    assert K.ktau_plain_default_q(64, 128) == 16
+    assert K.ktau_plain_default_q(16384, 8192) == 4
+    assert K.ktau_plain_default_q(353, 17941) == 2
+
+
 def test_workspace_size_grows_with_shape():
     a = K.ktau_allpairs_workspace_size(64, 128)
     b = K.ktau_allpairs_workspace_size(16384, 1024)

@@ -157,3 +157,26 @@ def test_uneven_batch_sampled():
             assert np.array_equal(got[k][J], want[k]), (i, k)
         assert np.array_equal(got["tau_b"][J], want["tau_b"], equal_nan=True)
     b.close()
+
+
+def test_large_matrix_takes_the_tile_launch(tmp_path):
+    # a matrix of 8192 rows or more on a network scheme runs as a plain tile
+    # launch inside the batch (16 x 16 tiles); its neighbours of the same
+    # scheme keep the persistent kernel; all equal the plain calls bit for bit
+    shapes = [(8300, 300), (700, 300), (40, 280), (9000, 1000)]
+    mats = [synth.batch_matrix(sh, 43, i) for i, sh in enumerate(shapes)]
+    dev = [torch.from_numpy(X).cuda() for X in mats]
+    b = K.KtauBatch(dev, tune_cache=str(tmp_path / "tune.txt"))
+    for _ in range(2):
+        b.run()
+        assert b.status() == K.KTAU_OK
+        for i, Xd in enumerate(dev):
+            want = K.ktau_allpairs(Xd)
+            got = b.outs[i]
+            for k in ("nc", "nd", "n3", "n1"):
+                assert torch.equal(got[k], want[k]), (i, k, b.plan(i))
+            assert torch.equal(got["tau_b"].isnan(), want["tau_b"].isnan())
+            ok = ~want["tau_b"].isnan()
+            assert torch.equal(got["tau_b"][ok], want["tau_b"][ok]), (i, b.plan(i))
+    b.close()
+

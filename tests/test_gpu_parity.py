@@ -469,7 +469,8 @@ def test_paper_orientations_sampled(shape):
 @pytest.mark.slow
 def test_gene_expression_scale_batched_equals_plain():
     # the launch configuration bench.py reports as its value: a one-matrix
-    # batched plan (autotuned scheme, persistent kernel, hipGraph), replayed
+    # batched plan (autotuned scheme, the tile launch of a matrix of 8192 rows
+    # or more, hipGraph), replayed
     # twice; every output equals the plain call's (itself checked against the
     # oracle on samples above)
     X = synth.config_matrix(3)
