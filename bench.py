@@ -705,9 +705,12 @@ def main() -> int:
                    "valu_published": INT_VALU_OPS,
                    "lds_bytes_per_s": probes["lds_bytes_per_s"],
                    "lds_reference_128B_per_clk": LDS_BYTES_PER_S,
+                   "issue_per_simd_cycle": {
+                       k: v / (1024 * 2.4e9) for k, v in probes["issue_wave_instr_per_s"].items()},
                    "note": "the VALU probe issues 16 v_add_u32 per iteration (ISA); its rate "
                            "is a denominator only where it does not exceed 256 CUs x 64 "
-                           "lanes x 2.4 GHz"},
+                           "lanes x 2.4 GHz; issue_per_simd_cycle: wave instructions per "
+                           "SIMD and cycle at 2.4 GHz of each kind (0.25 = one per 4 cycles)"},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,

@@ -495,6 +495,16 @@ int ktau_probe_lds_bytes_per_iter(void);
 int ktau_probe_valu(uint32_t* out_dev, int64_t blocks, int iters, void* stream);
 int ktau_probe_lds(uint32_t* out_dev, int64_t blocks, int iters, void* stream);
 
+/* Issue-rate probe: as the VALU probe, with the 16 chains per lane built from
+ * one instruction kind: 0 int32 add (v_add_u32), 1 packed f16 minimum with a
+ * negated operand (v_pk_minimum3_f16), 2 unsigned 16-bit dot product with
+ * accumulate (v_dot2_u32_u16), 3 packed u16 minimum and add (v_pk_min_u16,
+ * v_pk_add_u16).  ktau_probe_issue_instrs_per_iter gives the wave
+ * instructions per wave and iteration of a kind (-1: no such kind);
+ * KTAU_EINVAL as ktau_probe_valu, or for a kind outside 0..3. */
+int ktau_probe_issue_instrs_per_iter(int kind);
+int ktau_probe_issue(uint32_t* out_dev, int64_t blocks, int iters, int kind, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

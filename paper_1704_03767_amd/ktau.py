@@ -75,6 +75,8 @@ def _declare(lib):
         "ktau_probe_valu_ops_per_iter": ([], i32),
         "ktau_probe_lds_bytes_per_iter": ([], i32),
         "ktau_probe_valu": ([p, i64, i32, p], i32),
+        "ktau_probe_issue": ([p, i64, i32, i32, p], i32),
+        "ktau_probe_issue_instrs_per_iter": ([i32], i32),
         "ktau_probe_lds": ([p, i64, i32, p], i32),
         "ktau_perm_test": ([p, i64, i64, p, i64, i64, i64, p, p, p, sz, p], i32),
     }
@@ -502,6 +504,16 @@ def probe_peaks(blocks: int = 2048, valu_iters: int = 20000, lds_iters: int = 20
     l_ms = best(L.ktau_probe_lds, lds_iters)
     ops = blocks * threads * L.ktau_probe_valu_ops_per_iter() * valu_iters
     byt = blocks * threads * L.ktau_probe_lds_bytes_per_iter() * lds_iters
+    # wave instructions per second of each instruction kind of the issue probe
+    issue = {}
+    for kind, name in enumerate(ISSUE_KINDS):
+        ms = best(lambda o, b, i, s, kind=kind: L.ktau_probe_issue(o, b, i, kind, s), valu_iters)
+        waves = blocks * threads // 64
+        issue[name] = waves * L.ktau_probe_issue_instrs_per_iter(kind) * valu_iters / (ms * 1e-3)
     return {"valu_lane_ops_per_s": ops / (v_ms * 1e-3), "lds_bytes_per_s": byt / (l_ms * 1e-3),
-            "valu_ms": v_ms, "lds_ms": l_ms}
+            "valu_ms": v_ms, "lds_ms": l_ms, "issue_wave_instr_per_s": issue}
+
+
+# Instruction kinds of the issue-rate probe, in the library's order.
+ISSUE_KINDS = ("v_add_u32", "v_pk_minimum3_f16", "v_dot2_u32_u16", "v_pk_min_u16+v_pk_add_u16")
 
