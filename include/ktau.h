@@ -259,8 +259,10 @@ int ktau_allpairs_ex(const float* X_dev, int64_t m, int64_t n, int64_t J_begin,
  * of any matrix of the class from atomic counters -- the shared-counter
  * distribution that Sec. 4.1 names for jobs of varied cost; one counter per
  * XCD's stretch of the tiles, with stealing between stretches -- so small
- * matrices do not leave the device idle.  The launch sequence (status clear, one pre-pass over all rows, the
- * persistent pair kernel, the heavy-tie composite pass) is captured in a
+ * matrices do not leave the device idle.  A matrix of 8192 rows or more on a
+ * network scheme runs instead as a plain tile launch of its own (a workgroup
+ * per 16 x 16 tile).  The launch sequence (status clear, one pre-pass over
+ * all rows, the pair kernels, the heavy-tie composite pass) is captured in a
  * hipGraph on the first ktau_batch_run and replayed afterwards.
  * ------------------------------------------------------------------------- */
 
