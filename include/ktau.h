@@ -261,7 +261,7 @@ int ktau_allpairs_ex(const float* X_dev, int64_t m, int64_t n, int64_t J_begin,
  * XCD's stretch of the tiles, with stealing between stretches -- so small
  * matrices do not leave the device idle.  A matrix of 8192 rows or more on a
  * network scheme runs instead as a plain tile launch of its own (a workgroup
- * per 16 x 16 tile).  The launch sequence (status clear, one pre-pass over
+ * per tile; a tuned tile edge of 8 or more becomes 16).  The launch sequence (status clear, one pre-pass over
  * all rows, the pair kernels, the heavy-tie composite pass) is captured in a
  * hipGraph on the first ktau_batch_run and replayed afterwards.
  * ------------------------------------------------------------------------- */
