@@ -235,6 +235,9 @@ int ktau_status(void* workspace_dev, void* stream);
  * samples); the permutation test does not. */
 #define KTAU_SCHEME_NAIVE 100
 
+/* The numbered pair schemes: ways of running Sec. 3.2 Steps 1-5 for one pair
+ * on a group of lanes (Step 3's count on a tagged sorting network, or on a
+ * network per chunk and merge paths above it for long rows). */
 int ktau_scheme_count(void);
 const char* ktau_scheme_name(int scheme);      /* "invalid" if out of range   */
 int64_t ktau_scheme_capacity(int scheme);      /* largest n; -1 if invalid    */
@@ -390,7 +393,8 @@ int ktau_query(const ktau_db* db, const float* Q_dev, int64_t nq, int64_t k,
                void* workspace_dev, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Query server: continuous batching over a resident database.
+ * Query server: continuous batching over a resident database, serving the
+ * query-vs-database search of Sec. 1 (ktau_query per launch).
  *
  * Requests (1..many query rows each, a k each) are queued in arrival order by
  * ktau_server_submit and served by a worker thread inside the library.  When
@@ -481,6 +485,8 @@ void ktau_server_destroy(ktau_server* server);
 /* ---------------------------------------------------------------------------
  * Diagnostics: kernels with a known amount of work per launch, for the
  * callers' own measurement of the peaks the rooflines are quoted against.
+ * They are not part of the paper's method (no passage defines them); Sec. 5
+ * is where the paper reports its own kernels' rates.
  * ------------------------------------------------------------------------- */
 
 /* Threads per workgroup of the probes, int32 adds per thread per iteration of
