@@ -58,6 +58,11 @@ def test_host_side_argument_errors():
                               None) == K.KTAU_EINVAL       # wave_k2 holds n <= 128
     assert L.ktau_allpairs_ex(fake, 30, 30, -1, -1, _out(), ws, 1 << 30, 99, 0,
                               None) == K.KTAU_EINVAL
+    # the issue-rate probe: kinds 0..3 only, checked before any launch
+    assert L.ktau_probe_issue(fake, 1, 1, 4, None) == K.KTAU_EINVAL
+    assert L.ktau_probe_issue(fake, 1, 1, -1, None) == K.KTAU_EINVAL
+    assert L.ktau_probe_issue(None, 1, 1, 0, None) == K.KTAU_EINVAL
+    assert [L.ktau_probe_issue_instrs_per_iter(k) for k in range(-1, 5)] == [-1, 16, 16, 16, 32, -1]
     assert L.ktau_allpairs_ex(fake, 30, 30, -1, -1, _out(), ws, 1 << 30, -1, 65,
                               None) == K.KTAU_EINVAL
     # the naive bit-set scheme takes rows of at most 256 samples
