@@ -471,11 +471,20 @@ struct NetS {
     return c;
   }
 
+  // Element lane bit lb sits on physical lane bit lb: bits 0-4 exchange by
+  // ds_swizzle (one minimum per VGPR under a sign pattern), bit 5 of a whole
+  // wave by v_permlane32_swap (a minimum and a maximum per two VGPRs, signs
+  // plain); bit 5 is the top level's, which is mostly taken from global
+  // ranks.  (The integer network puts its most used lane bits on the permlane
+  // swaps instead.)
+  static constexpr int phys_bit(int lb) { return lb; }
+  static __device__ __forceinline__ int logical_lane(int plane) { return plane; }
+
   // Stage on element bit k: takes a sign pattern (the upper partner negated)
   // or needs both partners positive (permlane stages); register stages take
   // whatever signs their partners share.
   static constexpr bool patterned(int k) {
-    return k == LOGKV || (k >= LOGK && (B::phys_bit(k - LOGK) < 4 || B::phys_bit(k - LOGK) > 5));
+    return k == LOGKV || (k >= LOGK && phys_bit(k - LOGK) != 5);
   }
   static constexpr bool wants_plain(int k) { return k >= LOGK && !patterned(k); }
 
@@ -510,33 +519,22 @@ struct NetS {
       }
     } else {
       constexpr int lb = k - LOGK;
-      constexpr int pb = B::phys_bit(lb);
-      if constexpr (pb < 4) {
+      constexpr int pb = phys_bit(lb);
+      if constexpr (pb < 5) {
 #pragma unroll
         for (int j = 0; j < KV; ++j) v[j] = fmn_neg(v[j], lane_xor<(1 << pb)>(v[j]));
-      } else if constexpr (pb == 4 || pb == 5) {
+      } else if constexpr (pb == 5) {
+        // two VGPRs at a time: the swap brings both partners into one lane,
+        // which keeps the minimum in one VGPR and the maximum in the other,
+        // and the swap back returns them (signs plain: both positive or both
+        // negated by the block's orientation)
 #pragma unroll
         for (int j = 0; j < KV; j += 2) {
-          uint32_t a = v[j], b = v[j + 1];
-          if constexpr (pb == 4) {
-            auto s = __builtin_amdgcn_permlane16_swap(a, b, false, false);
-            a = s[0];
-            b = s[1];
-          } else {
-            auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
-            a = s[0];
-            b = s[1];
-          }
-          const uint32_t mn = fmn(a, b), mx = fmx(a, b);
-          if constexpr (pb == 4) {
-            auto s = __builtin_amdgcn_permlane16_swap(mn, mx, false, false);
-            v[j] = s[0];
-            v[j + 1] = s[1];
-          } else {
-            auto s = __builtin_amdgcn_permlane32_swap(mn, mx, false, false);
-            v[j] = s[0];
-            v[j + 1] = s[1];
-          }
+          auto s = __builtin_amdgcn_permlane32_swap(v[j], v[j + 1], false, false);
+          const uint32_t a = s[0], b = s[1];
+          auto r = __builtin_amdgcn_permlane32_swap(fmn(a, b), fmx(a, b), false, false);
+          v[j] = r[0];
+          v[j + 1] = r[1];
         }
       } else {
 #pragma unroll
@@ -718,7 +716,7 @@ struct NetS {
     // (an empty asm keeps them from being hoisted out of the loop of pairs
     // and held, or spilled, across it)
     asm volatile("" : "+v"(plane));
-    const int lane = B::logical_lane(plane);
+    const int lane = logical_lane(plane);
     constexpr uint32_t kScale = (1u << (kT - 1)) * 0x00010001u;
     uint32_t v[KV];
 #pragma unroll

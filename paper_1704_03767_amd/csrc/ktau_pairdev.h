@@ -307,6 +307,15 @@ __device__ __forceinline__ void gather_keys(const uint16_t* row, const uint32_t 
   }
 }
 
+// The counting network of a scheme: the half-precision one for groups of up
+// to one wave (256-lane blocks, whose exchanges between waves go through
+// LDS, keep the integer one).  Its lane mapping assigns each lane its K
+// sorted positions.
+template <int K, int G>
+constexpr bool kHalfNet = G <= 64 && K >= 4 && K * G <= 8192;
+template <int K, int G>
+using PairNet = std::conditional_t<kHalfNet<K, G>, bitonic::NetS<K, G>, bitonic::Net<K, G>>;
+
 // Tie groups of v up to which the top level's count is taken from global
 // ranks instead of the network's last merge.
 constexpr int kTopGroups = 2;
@@ -436,11 +445,8 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
                                                int64_t v, int n, uint32_t* xbuf,
                                                uint32_t* red, int lane, uint32_t& nd,
                                                uint32_t& n3) {
-  // the half-precision network for groups of up to 32 lanes (measured faster
-  // there; whole waves and blocks, whose lowest lane bits exchange by
-  // permlane swaps, keep the integer network)
-  constexpr bool kHalf = G <= 32 && K * G <= 8192;
-  using Net = std::conditional_t<kHalf, bitonic::NetS<K, G>, bitonic::Net<K, G>>;
+  constexpr bool kHalf = kHalfNet<K, G>;
+  using Net = PairNet<K, G>;
   constexpr uint32_t kBias = kHalf ? bitonic::kHalfKeyBias : 0u;
   constexpr int kShift = kHalf ? bitonic::half_tag_bits(K * G) : 1;
   constexpr int KV = K / 2;
@@ -514,7 +520,7 @@ __device__ __forceinline__ void count_gathered(bitonic::u16x2 (&key)[K / 2], uin
     TopGroups tg;
     top_groups(rv_v, v, ngroups, n, kBias, kShift, tg);
     const uint32_t t = top_share<K, kBias, kShift>(key, ngroups, tg, eqs);
-    if (bitonic::Net<K, G>::logical_lane(lane) < G / 2) share += t;
+    if (Net::logical_lane(lane) < G / 2) share += t;
     else eqs = 0;
   }
   nd = group_sum<G>(share, red);
@@ -535,7 +541,7 @@ __device__ __forceinline__ bool pair_fast(const RankView& ry, int64_t y, const R
                                           int64_t x, int n, int64_t budget, uint32_t* lds,
                                           uint32_t* red, int lane, uint32_t& nd, uint32_t& n3) {
   using FL = FastLds<K, G>;
-  using Net = bitonic::Net<K, G>;
+  using Net = PairNet<K, G>;
   using bitonic::u16x2;
   constexpr int KV = K / 2;
   const int64_t n1y = ry.n1[y], n1x = rx.n1[x];

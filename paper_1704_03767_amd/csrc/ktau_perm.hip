@@ -82,7 +82,7 @@ template <int K, int G>
 __device__ __forceinline__ int64_t pair_perm(const PermDesc& d, int64_t y, int64_t x,
                                              uint32_t* lds, uint32_t* red, int lane) {
   using PL = PermLds<K, G>;
-  using Net = bitonic::Net<K, G>;
+  using Net = PairNet<K, G>;
   using bitonic::u16x2;
   constexpr int KV = K / 2;
   const RankView& rv = d.rv;

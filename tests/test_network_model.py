@@ -35,15 +35,11 @@ class Shape:
         self.T = half_tag_bits(self.N)
         self.kW = 12
 
-    def phys_bit(self, lb):
-        # whole waves put their two lowest element lane bits on the permlane
-        # swaps (physical bits 4 and 5)
-        if self.G >= 64:
-            return 4 if lb == 0 else 5 if lb == 1 else (lb - 2 if lb < 6 else lb)
-        return lb
-
     def patterned(self, k):
-        return k == self.LOGKV or (k >= self.LOGK and not 4 <= self.phys_bit(k - self.LOGK) <= 5)
+        # element lane bit lb is physical lane bit lb: bits 0-4 exchange by
+        # swizzles under a sign pattern, bit 5 (whole waves) by permlane swaps
+        # with plain signs
+        return k == self.LOGKV or (k >= self.LOGK and k - self.LOGK != 5)
 
     def plain(self, k):
         return k >= self.LOGK and not self.patterned(k)
@@ -236,7 +232,7 @@ def test_tag_bits():
 
 
 @pytest.mark.parametrize("K,G", [(4, 8), (8, 8), (16, 8), (8, 4), (16, 16), (32, 8), (4, 64),
-                                 (8, 32)])
+                                 (8, 32), (8, 64)])
 def test_network_counts_inversions(K, G):
     sh = Shape(K, G)
     N = K * G
