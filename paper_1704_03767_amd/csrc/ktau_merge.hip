@@ -52,16 +52,16 @@ constexpr uint32_t kHalf = 32768;
 // lanes read keys 32 to 64 positions apart; unpadded, such strides (64 or
 // 128 bytes) put every lane of a wave on the same LDS bank.  Padded, a
 // stride of 32 keys moves 17 dwords (a different bank per lane) and one of 64
-// keys 34 dwords (two lanes per bank).  The in-order row of the gather and
-// the in-run count stays unpadded.
+// keys 34 dwords (two lanes per bank).  The first pad slot after each block
+// holds the sentinel that a merge reads past the end of a run.  The in-order
+// row of the gather and the in-run count stays unpadded.
 __device__ __forceinline__ int padded(int p) { return p + ((p >> 6) << 2); }
 
 template <int K>
 struct MergeShape {
   static constexpr int kChunk = 64 * K;
   static int waves(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
-  // header, padded row, and 16 bytes of slack for the merge's reads one past
-  // a run
+  // header, padded row, and 16 bytes of slack
   static size_t lds_bytes(int waves) {
     const size_t keys = (size_t)waves * kChunk;
     return kMergeHdrWords * sizeof(uint32_t) + (keys + keys / 16) * sizeof(uint16_t) + 16;
@@ -173,15 +173,32 @@ __device__ __forceinline__ void merge_store_keys(uint16_t* row, int k0, const u1
   store_words<K>(row + k0, w);
 }
 
+// Byte offset in the padded row of the key at doubled position i2 = 2 p.
+// (one shift and one shift-add; left to itself the compiler used three)
+__device__ __forceinline__ uint32_t padded_byte(uint32_t i2) {
+  uint32_t o;
+  asm("v_lshl_add_u32 %0, %1, 3, %2" : "=v"(o) : "v"(i2 >> 7), "v"(i2));
+  return o;
+}
+
 // One lane's K outputs of the merge of sorted runs A (positions l0 ..
 // l0 + lenA - 1 of the padded row) and B (l0 + s .. l0 + s + lenB - 1),
 // starting at output position diag; returns the number of (A, B) pairs among
 // them with the A key strictly larger (for each B key taken, the A keys not
 // yet taken).  With kStore the merged keys are packed into w (output 2i low,
-// 2i + 1 high).  Every step loads the next key of the run it took from without
-// a branch; a load one past the end of a run stays inside the LDS row (runs
-// are contiguous, and the row has slack after it) and is replaced by the
-// sentinel.
+// 2i + 1 high).  Every run ends at a 64-key boundary, and the first slot of
+// the pad after it holds the sentinel: a head past the end of its run reads
+// that slot, since the byte offset of a position only grows with it and the
+// load takes the smaller of the head's offset and the run's pad slot.  The
+// lane keeps the doubled positions of both heads; each step loads the next
+// key of the run it took from.
+//
+// The count needs no work per B key: with nB(t) the B keys taken before step
+// t and lo the A keys before the segment, the B key taken at step t finds
+// lenA - lo - (t - nB(t)) A keys waiting, and the j-th B key taken has
+// nB(t) = j, so the count is nB (lenA - lo) - sum_{B steps} t + nB (nB - 1) / 2,
+// where sum_{B steps} t = nB (K - 1) - sum_t nB(t): a plain running sum of
+// B's head position.
 template <int K, bool kStore>
 __device__ __forceinline__ uint32_t merge_segment(const uint16_t* row, int l0, int s, int lenA,
                                                   int lenB, int diag, uint32_t (&w)[K / 2]) {
@@ -194,33 +211,43 @@ __device__ __forceinline__ uint32_t merge_segment(const uint16_t* row, int l0, i
     if (at(mid) <= at(s + diag - 1 - mid)) lo = mid + 1;
     else hi = mid;
   }
-  int rem = lenA - lo;           // A keys not yet taken
-  int ib = diag - lo;            // B keys taken
-  uint32_t a = rem > 0 ? at(lo) : kMergeSentinel;
-  uint32_t b = ib < lenB ? at(s + ib) : kMergeSentinel;
-  uint32_t cnt = 0, low = 0;
+  const char* base = (const char*)row;
+  const uint32_t limA = padded_byte(2u * (uint32_t)(l0 + lenA - 1)) + 2u;
+  const uint32_t limB = padded_byte(2u * (uint32_t)(l0 + s + lenB - 1)) + 2u;
+  auto load = [&](uint32_t i2, uint32_t lim) {
+    const uint32_t o = padded_byte(i2);
+    return (uint32_t)*(const uint16_t*)(base + (o < lim ? o : lim));
+  };
+  uint32_t ia2 = 2u * (uint32_t)(l0 + lo);               // A's head
+  uint32_t ib2 = 2u * (uint32_t)(l0 + s + diag - lo);    // B's head
+  const uint32_t ib0 = ib2;
+  uint32_t a = load(ia2, limA), b = load(ib2, limB);
+  uint32_t heads = 0, low = 0;   // heads: sum over steps of B's head
+  bool tb = false;
 #pragma unroll
   for (int t = 0; t < K; ++t) {
-    const bool tb = b < a;
+    heads += ib2;
+    // keep the sum a chain: reassociated, it held every step's terms live
+    asm volatile("" : "+v"(heads));
+    tb = b < a;
     if constexpr (kStore) {
       const uint32_t o = tb ? b : a;
       if (t & 1) w[t / 2] = low | (o << 16);
       else low = o;
     }
-    cnt += tb ? (uint32_t)rem : 0u;
-    // keep the sum a chain: reassociated, it held every step's terms live
-    asm volatile("" : "+v"(cnt));
     if (t + 1 < K) {
-      rem -= tb ? 0 : 1;
-      ib += tb ? 1 : 0;
-      const uint32_t raw = at(tb ? s + ib : lenA - rem);
-      const int left = tb ? lenB - ib : rem;   // keys left in the run just read
-      const uint32_t nv = left > 0 ? raw : kMergeSentinel;
+      const uint32_t nxt = (tb ? ib2 : ia2) + 2u;
+      ia2 = tb ? ia2 : nxt;
+      ib2 = tb ? nxt : ib2;
+      const uint32_t nv = load(nxt, tb ? limB : limA);
       a = tb ? a : nv;
       b = tb ? nv : b;
     }
   }
-  return cnt;
+  const uint32_t nb = ((ib2 - ib0) >> 1) + (tb ? 1u : 0u);
+  const uint32_t sum_nb = (heads - (uint32_t)K * ib0) >> 1;
+  const uint32_t sum_t = nb * (uint32_t)(K - 1) - sum_nb;
+  return nb * (uint32_t)(lenA - lo) - sum_t + nb * (nb - 1u) / 2u;
 }
 
 // The inverse of merge_store_keys: positions k0 .. k0+K-1 of the row, in the
@@ -357,6 +384,10 @@ __device__ __forceinline__ uint32_t merge_count(u16x2 (&key)[K / 2], uint16_t* r
     uint32_t w[KV];
     unpack_keys<K>(key, 0xFFFEFFFEu, w);
     store_words8<K>(row + padded(k0), w);
+    // the pad after each 64-key block holds the merge's sentinel
+    if (((k0 + K) & 63) == 0)
+      *(uint2*)(row + padded(k0 + K - 1) + 1) =
+          make_uint2(kMergeSentinel * 0x10001u, kMergeSentinel * 0x10001u);
   }
   __syncthreads();
   for (int s = C; s < NR; s <<= 1) {
