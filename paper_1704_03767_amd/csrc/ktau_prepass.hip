@@ -317,12 +317,30 @@ __device__ __forceinline__ void prepass_row_long(const float* __restrict__ X, in
   int npow2 = 2 * H;
   while (npow2 < n) npow2 <<= 1;
   for (int b = 0; b < npow2 / H; ++b) {
-    if (load_keys<T>(x, n, b * H, H, s_keys)) {
+    // A block with r < H samples (the last one, or none at all) sorts only
+    // the smallest power of two P >= r of its words, in the block's
+    // direction, and the rest of the block is padding: above every sample, it
+    // follows an ascending block's sorted words and precedes a descending
+    // one's.
+    const int r = n - b * H;
+    int P = H;
+    if (r < H) {
+      P = 1;
+      while (P < r) P <<= 1;
+    }
+    if (load_keys<T>(x, n, b * H, P, s_keys)) {
       if (threadIdx.x == 0) atomicExch(status, KTAU_ENAN);
       return;
     }
-    bitonic_stages<T>(s_keys, H, b * H, 2, H, 1);
-    for (int i = threadIdx.x; i < H; i += T) g[b * H + i] = s_keys[i];
+    const bool desc = (b & 1) != 0;
+    // a base with bit P set turns the last level descending and leaves the
+    // lower levels as at base 0 (b H has no bits below H)
+    bitonic_stages<T>(s_keys, P, desc ? P : 0, 2, P, 1);
+    const int off = desc ? H - P : 0;
+    for (int i = threadIdx.x; i < H; i += T) {
+      const int q = i - off;
+      g[b * H + i] = (q >= 0 && q < P) ? s_keys[q] : ~0ull;
+    }
     __syncthreads();
   }
   for (int k = 2 * H; k <= npow2; k <<= 1) {
